@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the Hessian action H m = F^T(noise_prec F m) + prior_prec m on one MI355X.
+
+Workload: FP32-complex stored operator, Nt=420 time blocks of Nd=100 x Nm=65536
+(F_k = N(0,1) exp(-k/60), seeded), one right-hand side m ~ N(0,1), noise_prec =
+prior_prec = 1.  One step = one H application (both passes over the 22 GB operator plus
+the transforms), inputs already resident in device memory.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def log(*a):
+    print("[bench %6.1fs]" % (time.time() - T0), *a, file=sys.stderr, flush=True)
+
+
+T0 = time.time()
+
+
+def algorithmic_bytes(Nt, Nd, Nm, nfreq, nspan, sb, vb):
+    """Bytes each kernel of one H application must move (see the design notes):
+    sb = bytes per stored complex entry, vb = bytes per vector real."""
+    cb = 2 * vb
+    vec_m = Nt * Nm * vb
+    spec_m = nfreq * Nm * cb
+    fhat = nfreq * Nd * Nm * sb
+    part = nfreq * nspan * Nd * cb
+    dh = nfreq * Nd * cb
+    return {
+        "fft_r2c_m": vec_m + spec_m,
+        "sbgemv_n": fhat + spec_m + part,
+        "dside_h": part + dh,
+        "sbgemv_c": fhat + dh + spec_m,
+        "fft_c2r_m": spec_m + 2 * vec_m + vec_m,
+    }
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+        return max(n) if n else 1
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--cpu-sample-cols", type=int, default=8192,
+                    help="parameter columns of the operator the CPU oracle is timed on")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    import paper_2407_13066_amd as bt
+    from paper_2407_13066_amd import build as btbuild
+
+    if not os.path.exists(bt.LIB_PATH):
+        btbuild.build()
+    bt.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wname = "fp32-nt420-nd100-nm65536"
+    w = synth.WORKLOADS[wname]
+    Nt, Nd, Nm, tau = w["Nt"], w["Nd"], w["Nm"], w["tau"]
+    noise_prec, prior_prec = w["noise_prec"], w["prior_prec"]
+    log("generating blocks [%d][%d][%d] FP64 (%.1f GB)" % (Nt, Nd, Nm, Nt * Nd * Nm * 8 / 1e9))
+    blocks = synth.blocks(Nt, Nd, Nm, tau)
+    m_host = synth.vectors(1, Nt, Nm, synth.STREAM_M)[0]
+    log("creating operator (FP32 complex storage)")
+    op = bt.btoep_create(blocks, w["storage"])
+    info = bt.btoep_query(op)
+    log("operator: L=%d nfreq=%d fhat=%.2f GB" % (info["L"], info["nfreq"], info["fhat_bytes"] / 1e9))
+
+    m = torch.from_numpy(m_host).to(dev, torch.float32)
+    Hm = torch.empty_like(m)
+    d = torch.empty((Nt, Nd), dtype=torch.float32, device=dev)
+    mt = torch.empty_like(m)
+    ws = torch.empty(bt.btoep_workspace_size(op, "H", 1), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        bt.btoep_apply_H(op, m, noise_prec, prior_prec, out=Hm, ws=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-kernel HIP events recorded on the launch stream
+    bt.btoep_profile_enable(op, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = bt.btoep_profile_read(op)
+    bt.btoep_profile_enable(op, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log("H: %.3f ms/step" % ms_per_step)
+
+    # F and F^T alone (context)
+    def time_call(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / reps
+
+    F_ms = time_call(lambda: bt.btoep_apply_F(op, m, d, ws=ws, stream=stream))
+    FT_ms = time_call(lambda: bt.btoep_apply_FT(op, d, mt, ws=ws, stream=stream))
+    log("F: %.3f ms, F^T: %.3f ms" % (F_ms, FT_ms))
+
+    nspan = -(-Nm // 4096)
+    ab = algorithmic_bytes(Nt, Nd, Nm, info["nfreq"], nspan, 8, 4)
+    H_bytes = sum(ab.values())
+    kernels = {}
+    for name, (n, tot) in kern.items():
+        avg = tot / max(n, 1)
+        key = "dside_h" if name == "dside_h" else name
+        kb = ab.get(key)
+        kernels[name] = {"launches": n, "avg_ms": round(avg, 4),
+                         "algorithmic_GBs": round(kb / (avg * 1e-3) / 1e9, 1) if kb else None}
+    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    dom_avg_s = kern[dom][1] / kern[dom][0] * 1e-3
+    achieved = ab[dom] / dom_avg_s / 1e9
+
+    result = {
+        "metric": "H matvecs/s + HBM GB/s (% of peak) at stated rel err; serving p50/p99 ms",
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "H matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded N(0,1) exp(-k/60) blocks, N(0,1) vector)",
+        "config": {"workload": wname, "Nt": Nt, "Nd": Nd, "Nm": Nm, "k": 1, "storage": "c64",
+                   "noise_prec": noise_prec, "prior_prec": prior_prec},
+        "H_algorithmic_GB": round(H_bytes / 1e9, 3),
+        "H_GBs": round(H_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "H_pct_hbm_peak": round(100 * H_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
+        "F_ms": round(F_ms, 4),
+        "FT_ms": round(FT_ms, 4),
+        "kernels": kernels,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+
+    if not args.no_check:
+        import oracle
+        log("checking sampled outputs against the FP64 oracle")
+        rng = np.random.default_rng(7)
+        Hm_h = Hm.double().cpu().numpy()
+        Fm_dev = bt.btoep_apply_F(op, m, d, ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        Fm_h = Fm_dev.double().cpu().numpy()
+        m32 = m.double().cpu().numpy()  # the FP32 input the device saw
+        Fm_ref = oracle.apply_F(blocks, m32)
+        idxH = [(int(rng.integers(Nt)), int(rng.integers(Nm))) for _ in range(64)]
+        ftd = oracle.entries_FT(blocks, noise_prec * Fm_ref, idxH)
+        Hs_ref = np.array([ftd[n] + prior_prec * m32[j, p] for n, (j, p) in enumerate(idxH)])
+        Hs = np.array([Hm_h[j, p] for (j, p) in idxH])
+        result["rel_err"] = {"F_full": oracle.rel_l2(Fm_h, Fm_ref),
+                             "H_sampled64": oracle.rel_l2(Hs, Hs_ref), "tolerance": 1e-5}
+        log("rel err F %.2e, H(sampled) %.2e" % (result["rel_err"]["F_full"], result["rel_err"]["H_sampled64"]))
+
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = min(args.cpu_sample_cols, Nm)
+        sb = np.ascontiguousarray(blocks[:, :, :ns])
+        ms_ = np.ascontiguousarray(m_host[:, :ns])
+        log("timing the CPU oracle on %d of %d parameter columns" % (ns, Nm))
+        a = time.perf_counter()
+        oracle.apply_H(sb, ms_, noise_prec, prior_prec)
+        t = time.perf_counter() - a
+        scale = Nm / ns
+        result["cpu_baseline"] = {"value": round(1.0 / (t * scale), 5), "unit": "H matvecs/s",
+                                  "cores": blas_threads(), "kind": "oracle",
+                                  "sample": "FP64 oracle H on the first %d of %d parameter columns (same Nt, Nd): "
+                                            "%.2f s, scaled x%.0f (cost is linear in Nm)" % (ns, Nm, t, scale)}
+        log("cpu oracle %.2f s on the sample" % t)
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

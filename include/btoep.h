@@ -1,0 +1,194 @@
+/*
+ * btoep -- FFT-based matvecs with block lower-triangular Toeplitz operators on AMD MI355X.
+ *
+ * The operator is the discrete parameter-to-observable map F of a linear time-invariant
+ * system (Venkat, Fernando, Henneking, Ghattas, arXiv 2407.13066, section 2.1,
+ * eq. ShiftInvariance): Nt x Nt blocks of size Nd x Nm, block (i, j) = F_{i-j} for i >= j
+ * and zero above the diagonal, given by its first block column F_0 .. F_{Nt-1}.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Indices are 0-based; output block i is the paper's d_{i+1} (section 2.1).
+ *  - Vectors are time-outer-space-inner (the paper's TOSI ordering, section 3.1):
+ *      m[r][j][p]  (r < k right-hand sides, j < Nt, p < Nm),   d[r][i][s]  (s < Nd),
+ *    dense, row-major, k right-hand sides stacked outermost.
+ *  - Vector element type: double for an operator stored as BTOEP_F64, float otherwise.
+ *  - All vector, workspace and operator pointers given to apply/cg calls are DEVICE
+ *    pointers on the operator's device.  Host pointers are accepted only where stated.
+ *  - Streams are hipStream_t values passed as `void*` (NULL = the default stream).  Apply
+ *    calls are asynchronous and stream-ordered; cg_solve returns when the solve is done.
+ *  - Workspace: pass `ws`/`ws_bytes` of at least btoep_workspace_size(); with ws == NULL
+ *    the operator's own workspace is used (grown on demand with hipMalloc, which
+ *    synchronises the device), and calls on the same operator must then not overlap.
+ *    Calls that pass their own workspaces may run concurrently on one operator: the
+ *    stored operator is read-only after btoep_create.
+ *  - Errors: arguments are validated before any kernel is launched; nothing is written on
+ *    error.  A HIP failure returns BTOEP_ERR_HIP and its text is kept for
+ *    btoep_last_error().  No exception crosses this interface.
+ */
+#ifndef BTOEP_H
+#define BTOEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct btoep_op_s* btoep_op;
+
+typedef enum {
+    BTOEP_OK = 0,
+    BTOEP_ERR_INVALID_ARG = 1,
+    BTOEP_ERR_OUT_OF_MEMORY = 2,
+    BTOEP_ERR_HIP = 3,
+    BTOEP_ERR_UNSUPPORTED = 4,
+    BTOEP_ERR_NOT_CONVERGED = 5,
+    BTOEP_ERR_WORKSPACE_TOO_SMALL = 6
+} btoep_status;
+
+/* Storage precision of the Fourier-space operator (complex FP64, FP32 or BF16 parts). */
+typedef enum { BTOEP_F64 = 0, BTOEP_F32 = 1, BTOEP_BF16 = 2 } btoep_dtype;
+
+/* Where an input given to btoep_create lives. */
+typedef enum { BTOEP_HOST = 0, BTOEP_DEVICE = 1 } btoep_memory;
+
+/* Operation selector for btoep_workspace_size and btoep_apply_batched. */
+typedef enum { BTOEP_APPLY_F = 0, BTOEP_APPLY_FT = 1, BTOEP_APPLY_H = 2, BTOEP_CG = 3 } btoep_which;
+
+/* Largest number of right-hand sides one btoep_apply_batched call accepts. */
+#define BTOEP_MAX_BATCH 64
+
+typedef struct {
+    int64_t Nt, Nd, Nm;
+    int64_t L;          /* padded transform length 2N, N >= Nt the smallest 7-smooth integer */
+    int64_t nfreq;      /* L/2 + 1 stored frequencies                                        */
+    int64_t ldF;        /* row stride (complex elements) of the stored operator               */
+    btoep_dtype storage;
+    btoep_dtype vector; /* BTOEP_F64 (double vectors) or BTOEP_F32 (float vectors)            */
+    size_t fhat_bytes;  /* device bytes of the stored operator                                */
+    int device;
+} btoep_info;
+
+/*
+ * Setup (paper section 3.2, Algorithm 1): zero-pad every time series F_k[s][p], k < Nt, to
+ * length L, transform it along time (computed in FP64) and store its L/2+1 non-redundant
+ * frequencies, rounded to nearest (ties to even) into `storage`:
+ *     Fhat_f[s][p] = sum_{k<Nt} F_k[s][p] exp(-2 pi i f k / L),  f = 0 .. L/2.
+ * The frequency-outer layout Fhat[f][s][p] is the paper's TOSI form of the transformed
+ * operator.
+ *   blocks : FP64 first block column, [Nt][Nd][Nm] row-major, blocks[k] = F_k; in host or
+ *            device memory per `where`.  Not retained; may be freed once the call returns.
+ *   stream : stream for the setup work; the call returns after it has completed.
+ *   out    : receives the new operator (owned by the caller; free with btoep_destroy).
+ * Uses the current HIP device.  Errors: INVALID_ARG (sizes < 1, null pointers),
+ * UNSUPPORTED (transform length beyond one workgroup: N > 4095), OUT_OF_MEMORY, HIP.
+ */
+btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* blocks, btoep_memory where,
+                          btoep_dtype storage, void* stream, btoep_op* out);
+
+/* Releases the operator and everything it owns (synchronises its device). */
+btoep_status btoep_destroy(btoep_op op);
+
+/* Shapes, layout and sizes of an operator. */
+btoep_status btoep_query(btoep_op op, btoep_info* info);
+
+/* Device bytes of workspace one call of `which` with k right-hand sides needs. */
+btoep_status btoep_workspace_size(btoep_op op, btoep_which which, int64_t k, size_t* bytes);
+
+/*
+ * d = F m (paper section 3.3, Algorithm 2 on one device): transform m along time (zero
+ * padded), multiply every frequency by Fhat_f, transform back and keep the first Nt
+ * samples, i.e. (F m)_i = sum_{j<=i} F_{i-j} m_j.
+ *   k : right-hand sides (k >= 0; k == 0 does nothing);  m : [k][Nt][Nm];  d : [k][Nt][Nd].
+ */
+btoep_status btoep_apply_F(btoep_op op, int64_t k, const void* m, void* d, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/*
+ * m = F^T d (paper section 3.4, Algorithm 3): the same steps with the conjugate transpose
+ * of every Fhat_f (eq. AdjointFFTMatvec), i.e. (F^T d)_j = sum_{i>=j} F_{i-j}^T d_i.
+ *   d : [k][Nt][Nd];  m : [k][Nt][Nm].
+ */
+btoep_status btoep_apply_FT(btoep_op op, int64_t k, const void* d, void* m, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * Hessian action (paper section 2.2, eq. LinearInverseProblem, with scalar weights):
+ *     Hm = F^T (noise_prec * F m) + prior_prec * m.
+ * Two passes over the stored operator; the time-domain truncation between them is applied
+ * on the device.  m and Hm : [k][Nt][Nm]; they must not overlap.
+ */
+btoep_status btoep_apply_H(btoep_op op, int64_t k, double noise_prec, double prior_prec, const void* m, void* Hm,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Pointer-array form of the three applies for right-hand sides that do not sit in one
+ * array (e.g. requests batched by a server): in[r] / out[r] (HOST arrays of k <=
+ * BTOEP_MAX_BATCH device pointers) each point at one [Nt][Nm] or [Nt][Nd] vector.
+ * `which` is BTOEP_APPLY_F, _FT or _H (noise_prec / prior_prec used by _H only).
+ * Results equal k separate calls (each right-hand side is computed independently).
+ */
+btoep_status btoep_apply_batched(btoep_op op, btoep_which which, int64_t k, const void* const* in,
+                                 void* const* out, double noise_prec, double prior_prec, void* ws, size_t ws_bytes,
+                                 void* stream);
+
+typedef struct {
+    double rtol;        /* stop when ||b - H x||_2 <= rtol ||b||_2 (true residual, FP64)       */
+    int max_outer;      /* refinement steps (outer loop)                                        */
+    int max_inner;      /* CG iterations per refinement step                                    */
+    double inner_rtol;  /* inner CG stops when its recurrence residual drops by this factor     */
+    int check_every;    /* inner iterations between host convergence checks (>= 1)             */
+} btoep_cg_opts;
+
+typedef struct {
+    int inner_iters;     /* CG iterations, all refinement steps                              */
+    int outer_iters;     /* refinement steps taken                                           */
+    int matvecs;         /* H applications (inner + residual)                                */
+    int converged;       /* 1 when the true residual met rtol                                */
+    double rel_residual; /* final ||b - H x|| / ||b|| computed with the refinement operator  */
+} btoep_cg_result;
+
+/*
+ * Solves H x = b for k right-hand sides by conjugate gradients (paper section 2.2) with
+ * iterative refinement: each outer step forms the true residual r = b - H_hi x in FP64
+ * with `op_hi`, runs CG on H_lo e = r with `op_lo` (vectors in op_lo's vector type, inner
+ * products and CG scalars in FP64), and updates x += e in FP64.  With op_hi == NULL, op_lo
+ * must be BTOEP_F64 and serves both roles (plain FP64 CG with a true-residual check).
+ *   b, x : FP64 device arrays [k][Nt][Nm]; x holds the initial guess and receives x.
+ *   results : HOST array of k entries (may be NULL).
+ * Returns BTOEP_ERR_NOT_CONVERGED (x still written) when some right-hand side missed rtol.
+ * op_lo and op_hi must have the same Nt, Nd, Nm and device.
+ */
+btoep_status btoep_cg_solve(btoep_op op_lo, btoep_op op_hi, int64_t k, double noise_prec, double prior_prec,
+                            const double* b, double* x, const btoep_cg_opts* opts, btoep_cg_result* results,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Per-kernel timing for measurement: while enabled, every kernel an apply launches on this
+ * operator is bracketed by HIP events recorded on the same stream.  btoep_profile_read waits
+ * for the recorded events and returns, per kernel name, the launches and the summed
+ * milliseconds since profiling was (re)enabled.  Enabling resets the totals.  Not for
+ * concurrent use on one operator.
+ */
+typedef struct {
+    char name[24];
+    int64_t launches;
+    double total_ms;
+} btoep_kernel_time;
+
+btoep_status btoep_profile_enable(btoep_op op, int enable);
+btoep_status btoep_profile_read(btoep_op op, btoep_kernel_time* out, int max, int* count);
+
+/* Static text for a status code. */
+const char* btoep_status_string(btoep_status s);
+
+/* Text of the last HIP error seen on this operator (or by the calling thread when op is NULL). */
+const char* btoep_last_error(btoep_op op);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTOEP_H */

@@ -1,0 +1,311 @@
+"""MI355X-native FFT matvecs with block lower-triangular Toeplitz operators.
+
+A thin ctypes binding over ``libbtoep.so`` (HIP, gfx950), the C interface declared in
+``include/btoep.h``.  Functions carry the C names; they only marshal arguments
+(torch device tensors, the current HIP stream) -- every step of the computation runs in
+the library's kernels.  There is no fallback: when the library is missing or cannot be
+loaded every call raises.
+
+Layouts (time-outer, right-hand sides outermost):
+  blocks [Nt][Nd][Nm] FP64,  m [k][Nt][Nm],  d [k][Nt][Nd]
+Vector dtype: float64 for an operator stored as "f64", float32 for "f32" and "bf16".
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbtoep.so")
+
+BTOEP_OK = 0
+BTOEP_ERR_NOT_CONVERGED = 5
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
+WHICH = {"F": 0, "FT": 1, "H": 2, "CG": 3}
+MAX_BATCH = 64
+
+_lib = None
+
+
+class BtoepError(RuntimeError):
+    def __init__(self, status, what, detail=""):
+        self.status = status
+        msg = "%s failed: %s" % (what, btoep_status_string(status))
+        if detail:
+            msg += " [%s]" % detail
+        super().__init__(msg)
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("Nt", ctypes.c_int64), ("Nd", ctypes.c_int64), ("Nm", ctypes.c_int64),
+                ("L", ctypes.c_int64), ("nfreq", ctypes.c_int64), ("ldF", ctypes.c_int64),
+                ("storage", ctypes.c_int), ("vector", ctypes.c_int), ("fhat_bytes", ctypes.c_size_t),
+                ("device", ctypes.c_int)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("check_every", ctypes.c_int)]
+
+
+class CgResult(ctypes.Structure):
+    _fields_ = [("inner_iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+def load_library(path=LIB_PATH):
+    """Load libbtoep.so (raises OSError when it is missing or unloadable)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError("libbtoep.so not built at %s (run __graft_entry__.build())" % path)
+    lib = ctypes.CDLL(path)
+    vp, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "btoep_create": ([i64, i64, i64, vp, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)], st),
+        "btoep_destroy": ([vp], st),
+        "btoep_query": ([vp, ctypes.POINTER(_Info)], st),
+        "btoep_workspace_size": ([vp, ctypes.c_int, i64, ctypes.POINTER(sz)], st),
+        "btoep_apply_F": ([vp, i64, vp, vp, vp, sz, vp], st),
+        "btoep_apply_FT": ([vp, i64, vp, vp, vp, sz, vp], st),
+        "btoep_apply_H": ([vp, i64, dbl, dbl, vp, vp, vp, sz, vp], st),
+        "btoep_apply_batched": ([vp, ctypes.c_int, i64, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, dbl, vp, sz,
+                                 vp], st),
+        "btoep_cg_solve": ([vp, vp, i64, dbl, dbl, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp,
+                            sz, vp], st),
+        "btoep_profile_enable": ([vp, ctypes.c_int], st),
+        "btoep_profile_read": ([vp, ctypes.POINTER(KernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], st),
+        "btoep_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "btoep_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check(status, what, op=None):
+    if status != BTOEP_OK:
+        lib = load_library()
+        detail = lib.btoep_last_error(op).decode() if lib else ""
+        raise BtoepError(status, what, detail)
+
+
+def btoep_status_string(status):
+    return load_library().btoep_status_string(int(status)).decode()
+
+
+def btoep_last_error(op=None):
+    return load_library().btoep_last_error(op.handle if isinstance(op, Op) else op).decode()
+
+
+class Op:
+    """Owning handle of a created operator (destroyed with btoep_destroy or on collection)."""
+
+    def __init__(self, handle, info):
+        self.handle = handle
+        self.info = info
+        self.Nt, self.Nd, self.Nm = info["Nt"], info["Nd"], info["Nm"]
+        self.storage = info["storage"]
+
+    @property
+    def vector_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.storage == "f64" else torch.float32
+
+    def destroy(self):
+        if self.handle:
+            load_library().btoep_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def btoep_create(blocks, storage="f32", stream=None):
+    """Set up the Fourier-space operator from the first block column ``blocks`` [Nt][Nd][Nm] (FP64).
+
+    ``blocks`` is a numpy array (host) or a torch float64 tensor (host or device).
+    """
+    import numpy as np
+    lib = load_library()
+    torch = _torch()
+    if isinstance(blocks, np.ndarray):
+        arr = np.ascontiguousarray(blocks, dtype=np.float64)
+        ptr, where, shape, keep = arr.ctypes.data, 0, arr.shape, arr
+    else:
+        t = blocks
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("blocks must be a contiguous float64 tensor")
+        ptr, where, shape, keep = t.data_ptr(), (1 if t.is_cuda else 0), tuple(t.shape), t
+    if len(shape) != 3:
+        raise ValueError("blocks must have shape [Nt][Nd][Nm]")
+    Nt, Nd, Nm = shape
+    h = ctypes.c_void_p()
+    st = lib.btoep_create(Nt, Nd, Nm, ctypes.c_void_p(ptr), where, STORAGE[storage], _stream(stream),
+                          ctypes.byref(h))
+    del keep
+    _check(st, "btoep_create")
+    return Op(h, btoep_query(h))
+
+
+def btoep_destroy(op):
+    op.destroy()
+
+
+def btoep_query(op):
+    lib = load_library()
+    info = _Info()
+    h = op.handle if isinstance(op, Op) else op
+    _check(lib.btoep_query(h, ctypes.byref(info)), "btoep_query")
+    names = {v: k for k, v in STORAGE.items()}
+    return dict(Nt=info.Nt, Nd=info.Nd, Nm=info.Nm, L=info.L, nfreq=info.nfreq, ldF=info.ldF,
+                storage=names[info.storage], vector=names[info.vector], fhat_bytes=info.fhat_bytes,
+                device=info.device)
+
+
+def btoep_workspace_size(op, which, k=1):
+    n = ctypes.c_size_t()
+    _check(load_library().btoep_workspace_size(op.handle, WHICH[which], int(k), ctypes.byref(n)),
+           "btoep_workspace_size", op.handle)
+    return n.value
+
+
+def _vec(op, t, tail, name):
+    torch = _torch()
+    if not t.is_cuda or t.dtype != op.vector_dtype or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, op.vector_dtype))
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or tuple(t.shape[1:]) != tail:
+        raise ValueError("%s has shape %s, expected [k]%s" % (name, tuple(t.shape), list(tail)))
+    return t
+
+
+def _ws(ws):
+    if ws is None:
+        return ctypes.c_void_p(None), 0
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
+def btoep_apply_F(op, m, d=None, ws=None, stream=None):
+    """d = F m.  m: [k][Nt][Nm] (or [Nt][Nm]); returns d [k][Nt][Nd] (same leading form)."""
+    torch = _torch()
+    squeeze = m.dim() == 2
+    m3 = _vec(op, m, (op.Nt, op.Nm), "m")
+    k = m3.shape[0]
+    if d is None:
+        d = torch.empty((k, op.Nt, op.Nd), dtype=m.dtype, device=m.device)
+    d3 = _vec(op, d, (op.Nt, op.Nd), "d")
+    wp, wn = _ws(ws)
+    _check(load_library().btoep_apply_F(op.handle, k, ctypes.c_void_p(m3.data_ptr()),
+                                        ctypes.c_void_p(d3.data_ptr()), wp, wn, _stream(stream)),
+           "btoep_apply_F", op.handle)
+    return d3[0] if squeeze else d
+
+
+def btoep_apply_FT(op, d, m=None, ws=None, stream=None):
+    """m = F^T d.  d: [k][Nt][Nd]; returns m [k][Nt][Nm]."""
+    torch = _torch()
+    squeeze = d.dim() == 2
+    d3 = _vec(op, d, (op.Nt, op.Nd), "d")
+    k = d3.shape[0]
+    if m is None:
+        m = torch.empty((k, op.Nt, op.Nm), dtype=d.dtype, device=d.device)
+    m3 = _vec(op, m, (op.Nt, op.Nm), "m")
+    wp, wn = _ws(ws)
+    _check(load_library().btoep_apply_FT(op.handle, k, ctypes.c_void_p(d3.data_ptr()),
+                                         ctypes.c_void_p(m3.data_ptr()), wp, wn, _stream(stream)),
+           "btoep_apply_FT", op.handle)
+    return m3[0] if squeeze else m
+
+
+def btoep_apply_H(op, m, noise_prec=1.0, prior_prec=1.0, out=None, ws=None, stream=None):
+    """Hm = F^T (noise_prec F m) + prior_prec m."""
+    torch = _torch()
+    squeeze = m.dim() == 2
+    m3 = _vec(op, m, (op.Nt, op.Nm), "m")
+    k = m3.shape[0]
+    if out is None:
+        out = torch.empty((k, op.Nt, op.Nm), dtype=m.dtype, device=m.device)
+    o3 = _vec(op, out, (op.Nt, op.Nm), "out")
+    wp, wn = _ws(ws)
+    _check(load_library().btoep_apply_H(op.handle, k, float(noise_prec), float(prior_prec),
+                                        ctypes.c_void_p(m3.data_ptr()), ctypes.c_void_p(o3.data_ptr()),
+                                        wp, wn, _stream(stream)),
+           "btoep_apply_H", op.handle)
+    return o3[0] if squeeze else out
+
+
+def btoep_apply_batched(op, which, ins, outs, noise_prec=1.0, prior_prec=1.0, ws=None, stream=None):
+    """Pointer-array apply: ins[r] / outs[r] are separate device tensors ([Nt][Nm] or [Nt][Nd])."""
+    k = len(ins)
+    if k != len(outs) or k > MAX_BATCH:
+        raise ValueError("need len(ins) == len(outs) <= %d" % MAX_BATCH)
+    PA = ctypes.c_void_p * max(k, 1)
+    pin = PA(*[t.data_ptr() for t in ins])
+    pout = PA(*[t.data_ptr() for t in outs])
+    wp, wn = _ws(ws)
+    _check(load_library().btoep_apply_batched(op.handle, WHICH[which], k, pin, pout, float(noise_prec),
+                                              float(prior_prec), wp, wn, _stream(stream)),
+           "btoep_apply_batched", op.handle)
+    return outs
+
+
+def btoep_cg_solve(op_lo, op_hi, b, x, noise_prec, prior_prec, rtol=1e-8, max_outer=10, max_inner=1000,
+                   inner_rtol=1e-4, check_every=4, ws=None, stream=None, raise_on_not_converged=False):
+    """Solve H x = b (FP64 b, x of shape [k][Nt][Nm] on the device; x is the initial guess).
+
+    Returns (status, [CgResult per right-hand side]).
+    """
+    torch = _torch()
+    for t, n in ((b, "b"), (x, "x")):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous float64 CUDA tensor" % n)
+    b3 = b if b.dim() == 3 else b.unsqueeze(0)
+    k = b3.shape[0]
+    opts = CgOpts(rtol, max_outer, max_inner, inner_rtol, check_every)
+    res = (CgResult * k)()
+    wp, wn = _ws(ws)
+    st = load_library().btoep_cg_solve(op_lo.handle, op_hi.handle if op_hi is not None else None, k,
+                                       float(noise_prec), float(prior_prec), ctypes.c_void_p(b.data_ptr()),
+                                       ctypes.c_void_p(x.data_ptr()), ctypes.byref(opts), res, wp, wn,
+                                       _stream(stream))
+    if st not in (BTOEP_OK, BTOEP_ERR_NOT_CONVERGED) or (st != BTOEP_OK and raise_on_not_converged):
+        _check(st, "btoep_cg_solve", op_lo.handle)
+    return st, [dict(inner_iters=r.inner_iters, outer_iters=r.outer_iters, matvecs=r.matvecs,
+                     converged=bool(r.converged), rel_residual=r.rel_residual) for r in res]
+
+
+def btoep_profile_enable(op, enable=True):
+    """Start (and reset) or stop per-kernel HIP-event timing on this operator."""
+    _check(load_library().btoep_profile_enable(op.handle, 1 if enable else 0), "btoep_profile_enable", op.handle)
+
+
+def btoep_profile_read(op):
+    """{kernel name: (launches, total ms)} since profiling was enabled (waits for the events)."""
+    buf = (KernelTime * 16)()
+    n = ctypes.c_int()
+    _check(load_library().btoep_profile_read(op.handle, buf, 16, ctypes.byref(n)), "btoep_profile_read", op.handle)
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(n.value)}

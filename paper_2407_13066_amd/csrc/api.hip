@@ -1,0 +1,642 @@
+// Host runtime behind the btoep C interface: operator objects, setup, workspace layout,
+// the apply pipelines of F, F^T and H, and the refined CG solver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "btoep.h"
+#include "blas1.h"
+#include "internal.h"
+
+using namespace btoep;
+
+struct btoep_op_s {
+    int device = 0;
+    int64_t Nt = 0, Nd = 0, Nm = 0, N = 0, L = 0, nfreq = 0, ldF = 0, ldv = 0;
+    btoep_dtype storage = BTOEP_F64;
+    Stor stor = Stor::C128;
+    Real vreal = Real::F64;
+    void* fhat = nullptr;
+    size_t fhat_bytes = 0;
+    FftPlan plan{};
+    void* tw64 = nullptr;  // exp(-2 pi i t / L), t < L, complex FP64
+    void* tw32 = nullptr;  // same, complex FP32
+    void* ws = nullptr;    // operator-owned workspace (used when the caller passes none)
+    size_t ws_cap = 0;
+    std::mutex mu;
+    char err[512] = {0};
+    // kernel timing (btoep_profile_*)
+    struct Pending {
+        int kid;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t prof_launches[16] = {0};
+    double prof_ms[16] = {0};
+};
+
+namespace {
+
+thread_local char g_err[512];
+
+void set_err(btoep_op op, const char* what, hipError_t e) {
+    char* dst = op ? op->err : g_err;
+    snprintf(dst, 512, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define BT_HIP(op, expr)                                  \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) {                           \
+            set_err((op), #expr, e_);                     \
+            return e_ == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP; \
+        }                                                 \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool is_7smooth(int64_t n) {
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Smallest 7-smooth N >= Nt: any padded length L = 2N >= 2Nt - 1 gives the exact linear
+// convolution; 2N keeps the even/odd real-transform packing.
+int64_t choose_N(int64_t Nt) {
+    int64_t n = std::max<int64_t>(Nt, 1);
+    while (!is_7smooth(n)) ++n;
+    return n;
+}
+
+bool make_plan(int64_t N, FftPlan& pl) {
+    pl = FftPlan{};
+    pl.N = (int)N;
+    int64_t n = N;
+    auto take = [&](int r) {
+        while (n % r == 0) {
+            if (pl.npass >= kMaxPass) return false;
+            pl.radix[pl.npass++] = r;
+            n /= r;
+        }
+        return true;
+    };
+    if (!take(8) || !take(4) || !take(2) || !take(5) || !take(3) || !take(7)) return false;
+    return n == 1;
+}
+
+size_t stor_bytes(Stor s) { return s == Stor::C128 ? 16 : (s == Stor::C64 ? 8 : 4); }
+size_t vbytes(const btoep_op op) { return op->vreal == Real::F64 ? 8 : 4; }
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int64_t nspan_of(const btoep_op op) {
+    const int cs = sbgemv_n_span(op->stor, op->Nm);
+    return (op->Nm + cs - 1) / cs;
+}
+
+// Workspace layout of one apply over nb right-hand sides.
+struct ApplyWs {
+    size_t vh = 0, part = 0, dh = 0, total = 0;
+};
+ApplyWs apply_layout(const btoep_op op, btoep_which which, int64_t nb) {
+    const size_t c = 2 * vbytes(op);
+    const size_t vh = align_up((size_t)nb * op->nfreq * op->ldv * c, 256);
+    const size_t part = align_up((size_t)nb * op->nfreq * nspan_of(op) * op->Nd * c, 256);
+    const size_t dh = align_up((size_t)nb * op->nfreq * op->Nd * c, 256);
+    ApplyWs w;
+    size_t off = 0;
+    w.vh = off;
+    off += vh;
+    if (which == BTOEP_APPLY_F || which == BTOEP_APPLY_H) {
+        w.part = off;
+        off += part;
+    }
+    if (which == BTOEP_APPLY_FT || which == BTOEP_APPLY_H) {
+        w.dh = off;
+        off += dh;
+    }
+    w.total = off;
+    return w;
+}
+
+// Workspace of a CG solve over nb right-hand sides.
+struct CgWs {
+    size_t sc = 0, tmp = 0, rhi = 0, r = 0, p = 0, Ap = 0, e = 0, apply = 0, total = 0;
+};
+CgWs cg_layout(const btoep_op lo, const btoep_op hi, int64_t nb) {
+    const size_t n = (size_t)lo->Nt * lo->Nm;
+    const size_t vl = vbytes(lo);
+    CgWs w;
+    size_t off = 0;
+    auto put = [&](size_t& slot, size_t bytes) {
+        slot = off;
+        off += align_up(bytes, 256);
+    };
+    put(w.sc, (size_t)nb * kScal * sizeof(double));
+    put(w.tmp, dot_tmp_doubles((int)nb) * sizeof(double));
+    put(w.rhi, (size_t)nb * n * sizeof(double));
+    put(w.r, (size_t)nb * n * vl);
+    put(w.p, (size_t)nb * n * vl);
+    put(w.Ap, (size_t)nb * n * vl);
+    put(w.e, (size_t)nb * n * vl);
+    const size_t a = std::max(apply_layout(lo, BTOEP_APPLY_H, nb).total,
+                              hi ? apply_layout(hi, BTOEP_APPLY_H, nb).total : (size_t)0);
+    put(w.apply, a);
+    w.total = off;
+    return w;
+}
+
+btoep_status get_ws(btoep_op op, size_t need, void*& ws, size_t& ws_bytes) {
+    if (ws) return ws_bytes >= need ? BTOEP_OK : BTOEP_ERR_WORKSPACE_TOO_SMALL;
+    std::lock_guard<std::mutex> lk(op->mu);
+    if (op->ws_cap < need) {
+        if (op->ws) (void)hipFree(op->ws);
+        op->ws = nullptr;
+        op->ws_cap = 0;
+        BT_HIP(op, hipMalloc(&op->ws, need));
+        op->ws_cap = need;
+    }
+    ws = op->ws;
+    ws_bytes = op->ws_cap;
+    return BTOEP_OK;
+}
+
+// Kernel identifiers for btoep_profile_read.
+enum Kid { K_R2C_M = 0, K_SBGEMV_N, K_DSIDE_F, K_DSIDE_H, K_SBGEMV_C, K_C2R_M, K_R2C_D, K_COUNT };
+const char* kid_name(int k) {
+    static const char* names[K_COUNT] = {"fft_r2c_m", "sbgemv_n", "dside_f", "dside_h",
+                                         "sbgemv_c", "fft_c2r_m", "fft_r2c_d"};
+    return (k >= 0 && k < K_COUNT) ? names[k] : "?";
+}
+
+hipEvent_t pool_event(btoep_op op) {
+    if (!op->pool.empty()) {
+        hipEvent_t e = op->pool.back();
+        op->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` on `st`, bracketed by events when profiling is on.
+template <typename Fn>
+hipError_t timed(btoep_op op, int kid, hipStream_t st, Fn&& fn) {
+    if (!op->prof) return fn();
+    hipEvent_t a = pool_event(op), b = pool_event(op);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    op->pending.push_back({kid, a, b});
+    return e;
+}
+
+const void* tw_of(const btoep_op op) { return op->vreal == Real::F64 ? op->tw64 : op->tw32; }
+Stor vstor(const btoep_op op) { return op->vreal == Real::F64 ? Stor::C128 : Stor::C64; }
+
+// One pipeline launch sequence over nb <= kMaxBatch right-hand sides.
+btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& in, const PtrBatch& out,
+                       double noise_prec, double prior_prec, char* ws, hipStream_t st) {
+    const ApplyWs w = apply_layout(op, which, nb);
+    void* vh = ws + w.vh;
+    void* part = ws + w.part;
+    void* dh = ws + w.dh;
+    const int Nt = (int)op->Nt, Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
+    const int nspan = (int)nspan_of(op);
+    const int64_t vh_b = op->nfreq * op->ldv, part_b = op->nfreq * nspan * op->Nd, dh_b = op->nfreq * op->Nd;
+    const double inv_n = 1.0 / (double)op->N;
+    const void* tw = tw_of(op);
+    PtrBatch none{};
+    if (which == BTOEP_APPLY_F || which == BTOEP_APPLY_H) {
+        BT_HIP(op, timed(op, K_R2C_M, st, [&] {
+            return launch_fft_r2c(op->vreal, op->vreal, vstor(op), in, Nm, nb, vh, op->ldv, vh_b, Nt, Nm, op->plan, tw,
+                                  st);
+        }));
+        BT_HIP(op, timed(op, K_SBGEMV_N, st, [&] {
+            return launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan,
+                                   part_b, st);
+        }));
+        if (which == BTOEP_APPLY_F) {
+            BT_HIP(op, timed(op, K_DSIDE_F, st, [&] {
+                return launch_dside(op->vreal, part, nspan, part_b, nb, &out, nullptr, 0, Nt, Nd, op->plan, tw, inv_n,
+                                    st);
+            }));
+            return BTOEP_OK;
+        }
+        BT_HIP(op, timed(op, K_DSIDE_H, st, [&] {
+            return launch_dside(op->vreal, part, nspan, part_b, nb, nullptr, dh, dh_b, Nt, Nd, op->plan, tw,
+                                noise_prec * inv_n, st);
+        }));
+        BT_HIP(op, timed(op, K_SBGEMV_C, st, [&] {
+            return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st);
+        }));
+        BT_HIP(op, timed(op, K_C2R_M, st, [&] {
+            return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, in, prior_prec, Nt, Nm, op->plan, tw,
+                                  inv_n, st);
+        }));
+        return BTOEP_OK;
+    }
+    // F^T
+    BT_HIP(op, timed(op, K_R2C_D, st, [&] {
+        return launch_fft_r2c(op->vreal, op->vreal, vstor(op), in, Nd, nb, dh, op->Nd, dh_b, Nt, Nd, op->plan, tw, st);
+    }));
+    BT_HIP(op, timed(op, K_SBGEMV_C, st, [&] {
+        return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st);
+    }));
+    BT_HIP(op, timed(op, K_C2R_M, st, [&] {
+        return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, none, 0.0, Nt, Nm, op->plan, tw, inv_n, st);
+    }));
+    return BTOEP_OK;
+}
+
+btoep_status apply_contig(btoep_op op, btoep_which which, int64_t k, const void* in, void* out, double noise_prec,
+                          double prior_prec, void* ws, size_t ws_bytes, void* stream) {
+    if (!op) return BTOEP_ERR_INVALID_ARG;
+    if (k < 0) return BTOEP_ERR_INVALID_ARG;
+    if (k == 0) return BTOEP_OK;
+    if (!in || !out) return BTOEP_ERR_INVALID_ARG;
+    if (which == BTOEP_APPLY_H && in == out) return BTOEP_ERR_INVALID_ARG;
+    const int64_t nb = std::min<int64_t>(k, kMaxBatch);
+    btoep_status s = get_ws(op, apply_layout(op, which, nb).total, ws, ws_bytes);
+    if (s != BTOEP_OK) return s;
+    DeviceGuard g(op->device);
+    const int64_t in_len = op->Nt * (which == BTOEP_APPLY_FT ? op->Nd : op->Nm);
+    const int64_t out_len = op->Nt * (which == BTOEP_APPLY_F ? op->Nd : op->Nm);
+    const size_t vb = vbytes(op);
+    for (int64_t r0 = 0; r0 < k; r0 += nb) {
+        const int n = (int)std::min<int64_t>(nb, k - r0);
+        PtrBatch pi{}, po{};
+        for (int r = 0; r < n; ++r) {
+            pi.p[r] = (const char*)in + (size_t)(r0 + r) * in_len * vb;
+            po.p[r] = (const char*)out + (size_t)(r0 + r) * out_len * vb;
+        }
+        s = run_apply(op, which, n, pi, po, noise_prec, prior_prec, (char*)ws, (hipStream_t)stream);
+        if (s != BTOEP_OK) return s;
+    }
+    return BTOEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* btoep_status_string(btoep_status s) {
+    switch (s) {
+        case BTOEP_OK: return "ok";
+        case BTOEP_ERR_INVALID_ARG: return "invalid argument";
+        case BTOEP_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case BTOEP_ERR_HIP: return "HIP runtime error";
+        case BTOEP_ERR_UNSUPPORTED: return "unsupported shape or option";
+        case BTOEP_ERR_NOT_CONVERGED: return "CG did not converge";
+        case BTOEP_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char* btoep_last_error(btoep_op op) { return op ? op->err : g_err; }
+
+btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* blocks, btoep_memory where,
+                          btoep_dtype storage, void* stream, btoep_op* out) {
+    if (!out) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (Nt < 1 || Nd < 1 || Nm < 1 || !blocks) return BTOEP_ERR_INVALID_ARG;
+    if (storage != BTOEP_F64 && storage != BTOEP_F32 && storage != BTOEP_BF16) return BTOEP_ERR_INVALID_ARG;
+    if (where != BTOEP_HOST && where != BTOEP_DEVICE) return BTOEP_ERR_INVALID_ARG;
+    if (Nd > 65535 || Nm > ((int64_t)1 << 30) || Nt > ((int64_t)1 << 20)) return BTOEP_ERR_UNSUPPORTED;
+    const int64_t N = choose_N(Nt);
+    FftPlan plan;
+    if (!make_plan(N, plan)) return BTOEP_ERR_UNSUPPORTED;
+    if (fft_log_cols((int)N, Real::F64) < 0) return BTOEP_ERR_UNSUPPORTED;
+
+    btoep_op op = new (std::nothrow) btoep_op_s();
+    if (!op) return BTOEP_ERR_OUT_OF_MEMORY;
+    if (hipGetDevice(&op->device) != hipSuccess) {
+        delete op;
+        return BTOEP_ERR_HIP;
+    }
+    op->Nt = Nt;
+    op->Nd = Nd;
+    op->Nm = Nm;
+    op->N = N;
+    op->L = 2 * N;
+    op->nfreq = N + 1;
+    op->ldF = (int64_t)align_up((size_t)Nm, 8);
+    op->ldv = op->ldF;
+    op->storage = storage;
+    op->stor = storage == BTOEP_F64 ? Stor::C128 : (storage == BTOEP_F32 ? Stor::C64 : Stor::BF16);
+    op->vreal = storage == BTOEP_F64 ? Real::F64 : Real::F32;
+    op->plan = plan;
+    hipStream_t st = (hipStream_t)stream;
+    auto fail = [&](btoep_status s) {
+        btoep_destroy(op);
+        return s;
+    };
+#define BT_CREATE(expr)                                              \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) {                                      \
+            set_err(nullptr, #expr, e_);                             \
+            return fail(e_ == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP); \
+        }                                                            \
+    } while (0)
+
+    // twiddles exp(-2 pi i t / L), t < L, from FP64 cos / sin
+    const int64_t L = op->L;
+    std::vector<double> t64(2 * L);
+    std::vector<float> t32(2 * L);
+    for (int64_t t = 0; t < L; ++t) {
+        const double a = -2.0 * M_PI * (double)t / (double)L;
+        t64[2 * t] = std::cos(a);
+        t64[2 * t + 1] = std::sin(a);
+        t32[2 * t] = (float)t64[2 * t];
+        t32[2 * t + 1] = (float)t64[2 * t + 1];
+    }
+    BT_CREATE(hipMalloc(&op->tw64, t64.size() * sizeof(double)));
+    BT_CREATE(hipMalloc(&op->tw32, t32.size() * sizeof(float)));
+    BT_CREATE(hipMemcpy(op->tw64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    BT_CREATE(hipMemcpy(op->tw32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+
+    op->fhat_bytes = (size_t)op->nfreq * Nd * op->ldF * stor_bytes(op->stor);
+    BT_CREATE(hipMalloc(&op->fhat, op->fhat_bytes));
+    if (op->ldF != Nm) BT_CREATE(hipMemsetAsync(op->fhat, 0, op->fhat_bytes, st));
+
+    const size_t sb = stor_bytes(op->stor);
+    const int64_t out_row = Nd * op->ldF;
+    if (where == BTOEP_DEVICE) {
+        BT_CREATE(launch_fft_r2c_strided(op->stor, blocks, Nd * Nm, Nm, (int)Nd, op->fhat, out_row, op->ldF, (int)Nt,
+                                         (int)Nm, plan, op->tw64, st));
+    } else {
+        // stage groups of sensor rows s: [Nt][sc][Nm] FP64 at most ~1 GiB per copy
+        const size_t per_s = (size_t)Nt * Nm * sizeof(double);
+        int64_t sc = std::max<int64_t>(1, std::min<int64_t>(Nd, (int64_t)((1ull << 30) / per_s)));
+        sc = std::min<int64_t>(sc, 65535);
+        void* stage = nullptr;
+        BT_CREATE(hipMalloc(&stage, (size_t)sc * per_s));
+        for (int64_t s0 = 0; s0 < Nd; s0 += sc) {
+            const int64_t ns = std::min<int64_t>(sc, Nd - s0);
+            hipError_t e = hipMemcpy2DAsync(stage, (size_t)ns * Nm * sizeof(double), blocks + s0 * Nm,
+                                            (size_t)Nd * Nm * sizeof(double), (size_t)ns * Nm * sizeof(double),
+                                            (size_t)Nt, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = launch_fft_r2c_strided(op->stor, (const double*)stage, ns * Nm, Nm, (int)ns,
+                                           (char*)op->fhat + (size_t)s0 * op->ldF * sb, out_row, op->ldF, (int)Nt,
+                                           (int)Nm, plan, op->tw64, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                set_err(nullptr, "staged setup", e);
+                (void)hipFree(stage);
+                return fail(e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP);
+            }
+        }
+        (void)hipFree(stage);
+    }
+    BT_CREATE(hipStreamSynchronize(st));
+#undef BT_CREATE
+    *out = op;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_destroy(btoep_op op) {
+    if (!op) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(op->device);
+    (void)hipDeviceSynchronize();
+    if (op->fhat) (void)hipFree(op->fhat);
+    if (op->tw64) (void)hipFree(op->tw64);
+    if (op->tw32) (void)hipFree(op->tw32);
+    if (op->ws) (void)hipFree(op->ws);
+    for (auto& p : op->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : op->pool) (void)hipEventDestroy(e);
+    delete op;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_query(btoep_op op, btoep_info* info) {
+    if (!op || !info) return BTOEP_ERR_INVALID_ARG;
+    info->Nt = op->Nt;
+    info->Nd = op->Nd;
+    info->Nm = op->Nm;
+    info->L = op->L;
+    info->nfreq = op->nfreq;
+    info->ldF = op->ldF;
+    info->storage = op->storage;
+    info->vector = op->vreal == Real::F64 ? BTOEP_F64 : BTOEP_F32;
+    info->fhat_bytes = op->fhat_bytes;
+    info->device = op->device;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_workspace_size(btoep_op op, btoep_which which, int64_t k, size_t* bytes) {
+    if (!op || !bytes || k < 0) return BTOEP_ERR_INVALID_ARG;
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(k, kMaxBatch));
+    switch (which) {
+        case BTOEP_APPLY_F:
+        case BTOEP_APPLY_FT:
+        case BTOEP_APPLY_H: *bytes = apply_layout(op, which, nb).total; return BTOEP_OK;
+        case BTOEP_CG: *bytes = cg_layout(op, nullptr, nb).total; return BTOEP_OK;
+    }
+    return BTOEP_ERR_INVALID_ARG;
+}
+
+btoep_status btoep_apply_F(btoep_op op, int64_t k, const void* m, void* d, void* ws, size_t ws_bytes, void* stream) {
+    return apply_contig(op, BTOEP_APPLY_F, k, m, d, 0.0, 0.0, ws, ws_bytes, stream);
+}
+
+btoep_status btoep_apply_FT(btoep_op op, int64_t k, const void* d, void* m, void* ws, size_t ws_bytes, void* stream) {
+    return apply_contig(op, BTOEP_APPLY_FT, k, d, m, 0.0, 0.0, ws, ws_bytes, stream);
+}
+
+btoep_status btoep_apply_H(btoep_op op, int64_t k, double noise_prec, double prior_prec, const void* m, void* Hm,
+                           void* ws, size_t ws_bytes, void* stream) {
+    return apply_contig(op, BTOEP_APPLY_H, k, m, Hm, noise_prec, prior_prec, ws, ws_bytes, stream);
+}
+
+btoep_status btoep_apply_batched(btoep_op op, btoep_which which, int64_t k, const void* const* in, void* const* out,
+                                 double noise_prec, double prior_prec, void* ws, size_t ws_bytes, void* stream) {
+    if (!op || k < 0 || k > kMaxBatch) return BTOEP_ERR_INVALID_ARG;
+    if (which != BTOEP_APPLY_F && which != BTOEP_APPLY_FT && which != BTOEP_APPLY_H) return BTOEP_ERR_INVALID_ARG;
+    if (k == 0) return BTOEP_OK;
+    if (!in || !out) return BTOEP_ERR_INVALID_ARG;
+    PtrBatch pi{}, po{};
+    for (int64_t r = 0; r < k; ++r) {
+        if (!in[r] || !out[r]) return BTOEP_ERR_INVALID_ARG;
+        if (which == BTOEP_APPLY_H && in[r] == out[r]) return BTOEP_ERR_INVALID_ARG;
+        pi.p[r] = in[r];
+        po.p[r] = out[r];
+    }
+    btoep_status s = get_ws(op, apply_layout(op, which, k).total, ws, ws_bytes);
+    if (s != BTOEP_OK) return s;
+    DeviceGuard g(op->device);
+    return run_apply(op, which, (int)k, pi, po, noise_prec, prior_prec, (char*)ws, (hipStream_t)stream);
+}
+
+btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_prec, double prior_prec,
+                            const double* b, double* x, const btoep_cg_opts* opts, btoep_cg_result* results, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (!lo || k < 0) return BTOEP_ERR_INVALID_ARG;
+    if (k == 0) return BTOEP_OK;
+    if (!b || !x) return BTOEP_ERR_INVALID_ARG;
+    if (!hi && lo->storage != BTOEP_F64) return BTOEP_ERR_INVALID_ARG;
+    if (hi && (hi->storage != BTOEP_F64 || hi->Nt != lo->Nt || hi->Nd != lo->Nd || hi->Nm != lo->Nm ||
+               hi->device != lo->device))
+        return BTOEP_ERR_INVALID_ARG;
+    btoep_cg_opts o{1e-8, 10, 1000, 1e-4, 4};
+    if (opts) o = *opts;
+    if (!(o.rtol > 0) || o.max_outer < 1 || o.max_inner < 1 || !(o.inner_rtol > 0) || o.check_every < 1)
+        return BTOEP_ERR_INVALID_ARG;
+    if (k > kMaxBatch) return BTOEP_ERR_UNSUPPORTED;
+    btoep_op H = hi ? hi : lo;
+    const int nb = (int)k;
+    const CgWs w = cg_layout(lo, hi, nb);
+    btoep_status s = get_ws(lo, w.total, ws, ws_bytes);
+    if (s != BTOEP_OK) return s;
+    DeviceGuard g(lo->device);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    double* sc = (double*)(base + w.sc);
+    double* tmp = (double*)(base + w.tmp);
+    double* rhi = (double*)(base + w.rhi);
+    void* r = base + w.r;
+    void* p = base + w.p;
+    void* Ap = base + w.Ap;
+    void* e = base + w.e;
+    char* aws = base + w.apply;
+    const size_t aws_bytes = w.total - w.apply;
+    const int64_t n = lo->Nt * lo->Nm;
+    const Real rl = lo->vreal;
+
+    double* hsc = nullptr;
+    BT_HIP(lo, hipHostMalloc((void**)&hsc, (size_t)nb * kScal * sizeof(double), hipHostMallocDefault));
+    struct HostFree {
+        double* p;
+        ~HostFree() {
+            if (p) (void)hipHostFree(p);
+        }
+    } hf{hsc};
+
+    std::vector<double> zeros((size_t)nb * kScal, 0.0);
+    BT_HIP(lo, hipMemcpyAsync(sc, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    BT_HIP(lo, launch_dot(Real::F64, b, b, n, nb, n, sc, kScBB, 0, tmp, st));
+
+    int outer = 0, inner_total = 0, matvecs = 0;
+    const double rtol2 = o.rtol * o.rtol;
+    bool all_conv = false;
+    for (;;) {
+        // true residual in FP64 with the refinement operator: rhi = b - H x
+        s = apply_contig(H, BTOEP_APPLY_H, k, x, rhi, noise_prec, prior_prec, aws, aws_bytes, stream);
+        if (s != BTOEP_OK) return s;
+        ++matvecs;
+        BT_HIP(lo, launch_axpbz(Real::F64, rhi, -1.0, Real::F64, rhi, 1.0, Real::F64, b, n, nb, n, st));
+        BT_HIP(lo, launch_dot(Real::F64, rhi, rhi, n, nb, n, sc, kScRH, 0, tmp, st));
+        BT_HIP(lo, hipMemcpyAsync(hsc, sc, (size_t)nb * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
+        BT_HIP(lo, hipStreamSynchronize(st));
+        all_conv = true;
+        for (int i = 0; i < nb; ++i)
+            if (hsc[i * kScal + kScRH] > rtol2 * hsc[i * kScal + kScBB]) all_conv = false;
+        if (all_conv || outer >= o.max_outer) break;
+        ++outer;
+        // inner CG on H_lo e = r, e0 = 0, vectors in the low operator's type
+        BT_HIP(lo, launch_axpbz(rl, r, 1.0, Real::F64, rhi, 0.0, Real::F64, nullptr, n, nb, n, st));
+        BT_HIP(lo, launch_axpbz(rl, e, 0.0, rl, r, 0.0, rl, nullptr, n, nb, n, st));
+        BT_HIP(lo, launch_axpbz(rl, p, 1.0, rl, r, 0.0, rl, nullptr, n, nb, n, st));
+        BT_HIP(lo, launch_dot(rl, r, r, n, nb, n, sc, kScRR, 0, tmp, st));
+        BT_HIP(lo, launch_cg_init_scalars(sc, nb, o.inner_rtol * o.inner_rtol, rtol2, st));
+        for (int it = 0; it < o.max_inner; ++it) {
+            s = apply_contig(lo, BTOEP_APPLY_H, k, p, Ap, noise_prec, prior_prec, aws, aws_bytes, stream);
+            if (s != BTOEP_OK) return s;
+            ++matvecs;
+            ++inner_total;
+            BT_HIP(lo, launch_dot(rl, p, Ap, n, nb, n, sc, kScPAP, kScPAP, tmp, st));
+            BT_HIP(lo, launch_cg_xr(rl, rl, e, r, p, Ap, n, nb, n, sc, st));
+            BT_HIP(lo, launch_dot(rl, r, r, n, nb, n, sc, kScRRN, kScRRN, tmp, st));
+            BT_HIP(lo, launch_cg_p(rl, p, r, n, nb, n, sc, st));
+            if ((it + 1) % o.check_every == 0) {
+                BT_HIP(lo, hipMemcpyAsync(hsc, sc, (size_t)nb * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
+                BT_HIP(lo, hipStreamSynchronize(st));
+                bool any = false;
+                for (int i = 0; i < nb; ++i) any |= hsc[i * kScal + kScACT] != 0.0;
+                if (!any) break;
+            }
+        }
+        BT_HIP(lo, launch_axpbz(Real::F64, x, 1.0, Real::F64, x, 1.0, rl, e, n, nb, n, st));
+    }
+    if (results) {
+        for (int i = 0; i < nb; ++i) {
+            const double bb = hsc[i * kScal + kScBB], rh = hsc[i * kScal + kScRH];
+            results[i].inner_iters = (int)hsc[i * kScal + kScIT];
+            results[i].outer_iters = outer;
+            results[i].matvecs = matvecs;
+            results[i].rel_residual = bb > 0 ? std::sqrt(rh / bb) : std::sqrt(rh);
+            results[i].converged = rh <= rtol2 * bb ? 1 : 0;
+        }
+    }
+    (void)inner_total;
+    return all_conv ? BTOEP_OK : BTOEP_ERR_NOT_CONVERGED;
+}
+
+btoep_status btoep_profile_enable(btoep_op op, int enable) {
+    if (!op) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(op->device);
+    for (auto& p : op->pending) {
+        (void)hipEventSynchronize(p.b);
+        op->pool.push_back(p.a);
+        op->pool.push_back(p.b);
+    }
+    op->pending.clear();
+    for (int i = 0; i < 16; ++i) {
+        op->prof_launches[i] = 0;
+        op->prof_ms[i] = 0.0;
+    }
+    op->prof = enable != 0;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_profile_read(btoep_op op, btoep_kernel_time* out, int max, int* count) {
+    if (!op || !count || max < 0 || (max > 0 && !out)) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(op->device);
+    for (auto& p : op->pending) {
+        BT_HIP(op, hipEventSynchronize(p.b));
+        float ms = 0.f;
+        BT_HIP(op, hipEventElapsedTime(&ms, p.a, p.b));
+        op->prof_launches[p.kid] += 1;
+        op->prof_ms[p.kid] += ms;
+        op->pool.push_back(p.a);
+        op->pool.push_back(p.b);
+    }
+    op->pending.clear();
+    int n = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (op->prof_launches[k] == 0) continue;
+        if (n < max) {
+            snprintf(out[n].name, sizeof(out[n].name), "%s", kid_name(k));
+            out[n].launches = op->prof_launches[k];
+            out[n].total_ms = op->prof_ms[k];
+        }
+        ++n;
+    }
+    *count = std::min(n, max);
+    return BTOEP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,536 @@
+// Batched FFTs along the time axis of block-Toeplitz vectors and block columns.
+//
+// The method (paper section 2.4, section 3.3) zero-pads every length-Nt time series to
+// L = 2N (N >= Nt), transforms it, and after the per-frequency product transforms back and
+// keeps the first Nt samples.  Here a length-L real transform is one complex transform of
+// half length N on z[n] = x[2n] + i x[2n+1] (even/odd packing), followed by the usual
+// split into the L/2 + 1 = N + 1 non-redundant bins.  The complex transform is a
+// mixed-radix Stockham autosort FFT (radices 2, 3, 4, 5, 7, 8) run entirely in LDS: a
+// workgroup owns P consecutive columns (the contiguous axis of the time-outer layout), so
+// every global load and store is a run of P consecutive elements of one time row (or one
+// frequency row) and the time-outer <-> frequency-outer reordering of the paper's
+// SOTI/TOSI steps costs nothing extra.  Layout in LDS: element (n, c) at n*P + c.
+#include "common.h"
+#include "internal.h"
+
+namespace btoep {
+
+// ----------------------------------------------------------------------------------------
+// Small DFTs in registers:  y_t = sum_q x_q exp(DIR * 2 pi i q t / R), DIR = -1 forward.
+template <int R, int DIR, typename T>
+struct Dft;
+
+template <int DIR, typename T>
+struct Dft<2, DIR, T> {
+    __device__ static void run(cx<T>* v) {
+        cx<T> a = v[0];
+        v[0] = cadd(a, v[1]);
+        v[1] = csub(a, v[1]);
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<4, DIR, T> {
+    __device__ static void run(cx<T>* v) {
+        cx<T> a0 = cadd(v[0], v[2]), a1 = cadd(v[1], v[3]);
+        cx<T> b0 = csub(v[0], v[2]), b1 = cmul_i<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(a0, a1);
+        v[2] = csub(a0, a1);
+        v[1] = cadd(b0, b1);
+        v[3] = csub(b0, b1);
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<8, DIR, T> {
+    __device__ static void run(cx<T>* v) {
+        const T h = (T)0.70710678118654752440;  // 1/sqrt(2)
+        cx<T> a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = cadd(v[q], v[q + 4]);
+            b[q] = csub(v[q], v[q + 4]);
+        }
+        // b_q *= exp(DIR * 2 pi i q / 8)
+        b[1] = cx<T>{h * (b[1].re - DIR * b[1].im), h * (b[1].im + DIR * b[1].re)};
+        b[2] = cmul_i<DIR>(b[2]);
+        b[3] = cx<T>{h * (-b[3].re - DIR * b[3].im), h * (-b[3].im + DIR * b[3].re)};
+        Dft<4, DIR, T>::run(a);
+        Dft<4, DIR, T>::run(b);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[2 * u] = a[u];
+            v[2 * u + 1] = b[u];
+        }
+    }
+};
+
+// cos / sin of 2 pi n / R for the odd radices.
+template <int R>
+struct OddConst;
+template <>
+struct OddConst<3> {
+    __device__ static double c(int n) {
+        constexpr double t[3] = {1.0, -0.5, -0.5};
+        return t[n];
+    }
+    __device__ static double s(int n) {
+        constexpr double t[3] = {0.0, 0.8660254037844386, -0.8660254037844386};
+        return t[n];
+    }
+};
+template <>
+struct OddConst<5> {
+    __device__ static double c(int n) {
+        constexpr double t[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475,
+                                 0.30901699437494745};
+        return t[n];
+    }
+    __device__ static double s(int n) {
+        constexpr double t[5] = {0.0, 0.9510565162951535, 0.5877852522924731, -0.5877852522924731,
+                                 -0.9510565162951535};
+        return t[n];
+    }
+};
+template <>
+struct OddConst<7> {
+    __device__ static double c(int n) {
+        constexpr double t[7] = {1.0, 0.6234898018587335, -0.2225209339563144, -0.9009688679024191,
+                                 -0.9009688679024191, -0.2225209339563144, 0.6234898018587335};
+        return t[n];
+    }
+    __device__ static double s(int n) {
+        constexpr double t[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.4338837391175581,
+                                 -0.4338837391175581, -0.9749279121818236, -0.7818314824680298};
+        return t[n];
+    }
+};
+
+// Odd prime R: pair inputs q and R-q, a_q = x_q + x_{R-q}, b_q = x_q - x_{R-q};
+//   y_t     = x_0 + sum_q cos(2pi qt/R) a_q + DIR i sum_q sin(2pi qt/R) b_q
+//   y_{R-t} = x_0 + sum_q cos(2pi qt/R) a_q - DIR i sum_q sin(2pi qt/R) b_q
+template <int R, int DIR, typename T>
+struct DftOdd {
+    __device__ static void run(cx<T>* v) {
+        constexpr int H = (R - 1) / 2;
+        cx<T> a[H + 1], b[H + 1];
+        cx<T> y0 = v[0];
+#pragma unroll
+        for (int q = 1; q <= H; ++q) {
+            a[q] = cadd(v[q], v[R - q]);
+            b[q] = csub(v[q], v[R - q]);
+            y0 = cadd(y0, a[q]);
+        }
+        cx<T> out[R];
+        out[0] = y0;
+#pragma unroll
+        for (int t = 1; t <= H; ++t) {
+            cx<T> sc = v[0], ss = cx<T>{0, 0};
+#pragma unroll
+            for (int q = 1; q <= H; ++q) {
+                const T c = (T)OddConst<R>::c((q * t) % R);
+                const T s = (T)OddConst<R>::s((q * t) % R);
+                sc = cx<T>{fma(c, a[q].re, sc.re), fma(c, a[q].im, sc.im)};
+                ss = cx<T>{fma(s, b[q].re, ss.re), fma(s, b[q].im, ss.im)};
+            }
+            cx<T> iss = cmul_i<DIR>(ss);
+            out[t] = cadd(sc, iss);
+            out[R - t] = csub(sc, iss);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = out[r];
+    }
+};
+template <int DIR, typename T>
+struct Dft<3, DIR, T> : DftOdd<3, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<5, DIR, T> : DftOdd<5, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<7, DIR, T> : DftOdd<7, DIR, T> {};
+
+// ----------------------------------------------------------------------------------------
+// One Stockham pass of radix R over all P columns held in LDS.  Ns = product of the radices
+// already applied.  Butterfly j (< N/R) of column c reads elements j + r N/R, multiplies by
+// W_{Ns R}^{k r} (k = j mod Ns) and writes its outputs to (j - k) R + k + r Ns.  The
+// twiddle table holds exp(-2 pi i t / (2N)), t < 2N, so W_{Ns R}^{k r} is entry
+// 2 k r N / (Ns R).  Each thread keeps its butterflies in registers across the barrier,
+// which lets the pass run in place.
+template <typename T, int R, int DIR, int CMAX>
+__device__ __forceinline__ void stockham_pass(cx<T>* sh, int N, int logP, int Ns, const cx<T>* __restrict__ tw) {
+    constexpr int MAXB = (CMAX + R - 1) / R;
+    const int NR = N / R;
+    const int nbf = NR << logP;
+    const int stride = NR / Ns;
+    const int P1 = (1 << logP) - 1;
+    const int tid = threadIdx.x;
+    cx<T> v[MAXB][R];
+#pragma unroll
+    for (int bb = 0; bb < MAXB; ++bb) {
+        const int g = tid + bb * kFftThreads;
+        if (g < nbf) {
+            const int c = g & P1, j = g >> logP;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[bb][r] = sh[((j + r * NR) << logP) + c];
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[2 * (k * r * stride)];
+                    if (DIR > 0) w.im = -w.im;
+                    v[bb][r] = cmul(v[bb][r], w);
+                }
+            }
+            Dft<R, DIR, T>::run(v[bb]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < MAXB; ++bb) {
+        const int g = tid + bb * kFftThreads;
+        if (g < nbf) {
+            const int c = g & P1, j = g >> logP;
+            const int k = j % Ns;
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) sh[((base + r * Ns) << logP) + c] = v[bb][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int DIR, int CMAX>
+__device__ void fft_lds(cx<T>* sh, const FftPlan& plan, int logP, const cx<T>* __restrict__ tw) {
+    int Ns = 1;
+    for (int ip = 0; ip < plan.npass; ++ip) {
+        const int R = plan.radix[ip];
+        switch (R) {
+            case 2: stockham_pass<T, 2, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+            case 3: stockham_pass<T, 3, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+            case 4: stockham_pass<T, 4, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+            case 5: stockham_pass<T, 5, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+            case 7: stockham_pass<T, 7, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+            default: stockham_pass<T, 8, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+        }
+        Ns *= R;
+    }
+}
+
+template <typename T>
+struct FftCfg;
+template <>
+struct FftCfg<float> {
+    static constexpr int CMAX = 32;  // complex values per thread held across a pass
+};
+template <>
+struct FftCfg<double> {
+    static constexpr int CMAX = 16;
+};
+
+// ---- storing a complex value in each output format ----------------------------------
+template <typename T>
+__device__ __forceinline__ void put(cx<double>* p, cx<T> v) { *p = cx<double>{(double)v.re, (double)v.im}; }
+template <typename T>
+__device__ __forceinline__ void put(cx<float>* p, cx<T> v) { *p = cx<float>{(float)v.re, (float)v.im}; }
+template <typename T>
+__device__ __forceinline__ void put(bf16c* p, cx<T> v) {
+    *p = Store<bf16c>::from(cx<double>{(double)v.re, (double)v.im});
+}
+
+// Bins f = 0..N of the length-2N real transform from the half-length transform Z held in
+// LDS:  X_f = (Z_f + conj Z_{N-f}) / 2 + W_{2N}^f (Z_f - conj Z_{N-f}) / (2i).
+template <typename T>
+__device__ __forceinline__ cx<T> r2c_bin(const cx<T>* sh, int N, int logP, int f, int c, const cx<T>* tw) {
+    const int fa = (f == N) ? 0 : f;
+    const int fb = (f == 0) ? 0 : N - f;
+    cx<T> Z = sh[(fa << logP) + c];
+    cx<T> Zc = cconj(sh[(fb << logP) + c]);
+    cx<T> E = cscale(cadd(Z, Zc), (T)0.5);
+    cx<T> O = cmul_i<-1>(cscale(csub(Z, Zc), (T)0.5));
+    return cadd(E, cmul(tw[f], O));
+}
+
+// Inverse split, in place on LDS rows f and N-f: from bins Y_0..Y_N of a real signal build
+// Z_f = E_f + i O_f with E_f = (Y_f + conj Y_{N-f}) / 2 and O_f = (Y_f - conj Y_{N-f}) / 2 *
+// W_{2N}^{-f}; then the inverse half-length transform of Z gives x_{2n} + i x_{2n+1} (times N).
+template <typename T>
+__device__ __forceinline__ void c2r_split(cx<T>* sh, int N, int logP, const cx<T>* tw) {
+    const int P = 1 << logP;
+    const int npair = (N / 2 + 1) << logP;
+    for (int e = threadIdx.x; e < npair; e += kFftThreads) {
+        const int c = e & (P - 1), f = e >> logP;
+        const int g = N - f;
+        if (g < f) continue;  // only when N is odd: f = (N+1)/2 has no partner of its own
+        cx<T> Yf = sh[(f << logP) + c];
+        cx<T> Yg = sh[(g << logP) + c];
+        {
+            cx<T> b = cconj(Yg);
+            cx<T> E = cscale(cadd(Yf, b), (T)0.5);
+            cx<T> O = cmul(cscale(csub(Yf, b), (T)0.5), cconj(tw[f]));
+            sh[(f << logP) + c] = cadd(E, cmul_i<1>(O));
+        }
+        if (f != 0 && g != f) {
+            cx<T> b = cconj(Yf);
+            cx<T> E = cscale(cadd(Yg, b), (T)0.5);
+            cx<T> O = cmul(cscale(csub(Yg, b), (T)0.5), cconj(tw[g]));
+            sh[(g << logP) + c] = cadd(E, cmul_i<1>(O));
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// Forward: x (real, Nt rows) -> X (N+1 complex rows).
+template <typename T, typename Tin, typename So>
+__global__ __launch_bounds__(kFftThreads) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
+                                                         int64_t out_row, int64_t out_batch, int Nt, int ncols,
+                                                         FftPlan plan, int logP, const cx<T>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    T* shr = reinterpret_cast<T*>(smem_raw);
+    const int N = plan.N, P = 1 << logP;
+    const int col0 = blockIdx.x << logP;
+    const Tin* __restrict__ x = static_cast<const Tin*>(in.p[blockIdx.y]);
+    So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
+
+    for (int e = threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), j = e >> logP;
+        T val = (T)0;
+        if (j < Nt && col0 + c < ncols) val = (T)x[(int64_t)j * in_row + col0 + c];
+        shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = val;
+    }
+    __syncthreads();
+    fft_lds<T, -1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), f = e >> logP;
+        if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
+    }
+}
+
+// Setup form (operator block column, FP64 in, batch over rows s with explicit strides).
+template <typename So>
+__global__ __launch_bounds__(kFftThreads) void k_fft_r2c_strided(const double* __restrict__ in, int64_t in_row,
+                                                                 int64_t in_batch, So* __restrict__ out,
+                                                                 int64_t out_row, int64_t out_batch, int Nt,
+                                                                 int ncols, FftPlan plan, int logP,
+                                                                 const cx<double>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<double>* sh = reinterpret_cast<cx<double>*>(smem_raw);
+    double* shr = reinterpret_cast<double*>(smem_raw);
+    const int N = plan.N, P = 1 << logP;
+    const int col0 = blockIdx.x << logP;
+    const double* __restrict__ x = in + (int64_t)blockIdx.y * in_batch;
+    So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
+    for (int e = threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), j = e >> logP;
+        double val = 0.0;
+        if (j < Nt && col0 + c < ncols) val = x[(int64_t)j * in_row + col0 + c];
+        shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = val;
+    }
+    __syncthreads();
+    fft_lds<double, -1, FftCfg<double>::CMAX>(sh, plan, logP, tw);
+    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), f = e >> logP;
+        if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
+    }
+}
+
+// Inverse: X (N+1 complex rows) -> x_j for j < Nt, times out_scale, plus add_scale * addend.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_c2r(const cx<T>* __restrict__ in, int64_t in_row,
+                                                         int64_t in_batch, PtrBatch out, int64_t out_row,
+                                                         PtrBatch add, T add_scale, int Nt, int ncols,
+                                                         FftPlan plan, int logP, const cx<T>* __restrict__ tw,
+                                                         T out_scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    const T* shr = reinterpret_cast<const T*>(smem_raw);
+    const int N = plan.N, P = 1 << logP;
+    const int col0 = blockIdx.x << logP;
+    const cx<T>* __restrict__ y = in + (int64_t)blockIdx.y * in_batch;
+    T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.p[blockIdx.y]));
+    const T* __restrict__ a = static_cast<const T*>(add.p[blockIdx.y]);
+
+    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), f = e >> logP;
+        cx<T> v = cx<T>{0, 0};
+        if (col0 + c < ncols) v = y[(int64_t)f * in_row + col0 + c];
+        sh[(f << logP) + c] = v;
+    }
+    __syncthreads();
+    c2r_split<T>(sh, N, logP, tw);
+    __syncthreads();
+    fft_lds<T, 1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    for (int e = threadIdx.x; e < Nt << logP; e += kFftThreads) {
+        const int c = e & (P - 1), j = e >> logP;
+        if (col0 + c >= ncols) continue;
+        const int64_t o = (int64_t)j * out_row + col0 + c;
+        T v = out_scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
+        if (a) v = fma(add_scale, a[o], v);
+        x[o] = v;
+    }
+}
+
+// Data side: reduce split partial sums over spans, inverse transform, keep j < Nt, scale;
+// then either store d (F) or zero-pad, forward transform and store the bins (H).
+template <typename T, bool HMODE>
+__global__ __launch_bounds__(kFftThreads) void k_dside(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
+                                                       PtrBatch dout, cx<T>* __restrict__ dh, int64_t dh_batch,
+                                                       int Nt, int Nd, FftPlan plan, int logP,
+                                                       const cx<T>* __restrict__ tw, T scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    T* shr = reinterpret_cast<T*>(smem_raw);
+    const int N = plan.N, P = 1 << logP;
+    const int col0 = blockIdx.x << logP;
+    const cx<T>* __restrict__ pb = part + (int64_t)blockIdx.y * part_batch;
+
+    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), f = e >> logP;
+        cx<T> acc = cx<T>{0, 0};
+        if (col0 + c < Nd) {
+            const cx<T>* q = pb + (int64_t)f * nspan * Nd + col0 + c;
+            for (int sp = 0; sp < nspan; ++sp) acc = cadd(acc, q[(int64_t)sp * Nd]);
+        }
+        sh[(f << logP) + c] = acc;
+    }
+    __syncthreads();
+    c2r_split<T>(sh, N, logP, tw);
+    __syncthreads();
+    fft_lds<T, 1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    if (!HMODE) {
+        T* __restrict__ d = static_cast<T*>(const_cast<void*>(dout.p[blockIdx.y]));
+        for (int e = threadIdx.x; e < Nt << logP; e += kFftThreads) {
+            const int c = e & (P - 1), j = e >> logP;
+            if (col0 + c < Nd) d[(int64_t)j * Nd + col0 + c] = scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
+        }
+        return;
+    }
+    // keep samples j < Nt (scaled), zero the padding, transform forward again
+    for (int e = threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), j = e >> logP;
+        const int idx = 2 * (((j >> 1) << logP) + c) + (j & 1);
+        shr[idx] = (j < Nt) ? scale * shr[idx] : (T)0;
+    }
+    __syncthreads();
+    fft_lds<T, -1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    cx<T>* __restrict__ o = dh + (int64_t)blockIdx.y * dh_batch;
+    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
+        const int c = e & (P - 1), f = e >> logP;
+        if (col0 + c < Nd) o[(int64_t)f * Nd + col0 + c] = r2c_bin(sh, N, logP, f, c, tw);
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+static constexpr size_t kFftLdsBudget = 64 * 1024;
+
+int fft_log_cols(int N, Real r) {
+    const size_t elem = (r == Real::F64) ? 16 : 8;
+    const int cmax = (r == Real::F64) ? FftCfg<double>::CMAX : FftCfg<float>::CMAX;
+    for (int lp = 6; lp >= 0; --lp) {
+        const size_t P = (size_t)1 << lp;
+        if ((size_t)(N + 1) * P * elem <= kFftLdsBudget && (size_t)N * P <= (size_t)cmax * kFftThreads) return lp;
+    }
+    return -1;
+}
+
+size_t fft_lds_bytes(int N, int logP, Real r) {
+    const size_t elem = (r == Real::F64) ? 16 : 8;
+    return (size_t)(N + 1) * ((size_t)1 << logP) * elem;
+}
+
+static inline unsigned nblk(int n, int logP) { return (unsigned)((n + (1 << logP) - 1) >> logP); }
+
+hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_row, int nb, void* out,
+                          int64_t out_row, int64_t out_batch, int Nt, int ncols, const FftPlan& plan,
+                          const void* tw, hipStream_t st) {
+    const int lp = fft_log_cols(plan.N, r);
+    if (lp < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
+    const size_t lds = fft_lds_bytes(plan.N, lp, r);
+    if (r == Real::F32 && ir == Real::F32 && os == Stor::C64)
+        k_fft_r2c<float, float, cx<float>><<<grid, block, lds, st>>>(in, in_row, (cx<float>*)out, out_row,
+                                                                     out_batch, Nt, ncols, plan, lp,
+                                                                     (const cx<float>*)tw);
+    else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128)
+        k_fft_r2c<double, double, cx<double>><<<grid, block, lds, st>>>(in, in_row, (cx<double>*)out, out_row,
+                                                                        out_batch, Nt, ncols, plan, lp,
+                                                                        (const cx<double>*)tw);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int64_t in_batch, int nb, void* out,
+                                  int64_t out_row, int64_t out_batch, int Nt, int ncols, const FftPlan& plan,
+                                  const void* tw64, hipStream_t st) {
+    const int lp = fft_log_cols(plan.N, Real::F64);
+    if (lp < 0 || nb <= 0) return hipErrorInvalidValue;
+    dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
+    const size_t lds = fft_lds_bytes(plan.N, lp, Real::F64);
+    const cx<double>* tw = (const cx<double>*)tw64;
+    switch (os) {
+        case Stor::C128:
+            k_fft_r2c_strided<cx<double>><<<grid, block, lds, st>>>(in, in_row, in_batch, (cx<double>*)out,
+                                                                     out_row, out_batch, Nt, ncols, plan, lp, tw);
+            break;
+        case Stor::C64:
+            k_fft_r2c_strided<cx<float>><<<grid, block, lds, st>>>(in, in_row, in_batch, (cx<float>*)out, out_row,
+                                                                    out_batch, Nt, ncols, plan, lp, tw);
+            break;
+        case Stor::BF16:
+            k_fft_r2c_strided<bf16c><<<grid, block, lds, st>>>(in, in_row, in_batch, (bf16c*)out, out_row,
+                                                                out_batch, Nt, ncols, plan, lp, tw);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_batch, int nb, const PtrBatch& out,
+                          int64_t out_row, const PtrBatch& add, double add_scale, int Nt, int ncols,
+                          const FftPlan& plan, const void* tw, double out_scale, hipStream_t st) {
+    const int lp = fft_log_cols(plan.N, r);
+    if (lp < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
+    const size_t lds = fft_lds_bytes(plan.N, lp, r);
+    if (r == Real::F32)
+        k_fft_c2r<float><<<grid, block, lds, st>>>((const cx<float>*)in, in_row, in_batch, out, out_row, add,
+                                                   (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw,
+                                                   (float)out_scale);
+    else
+        k_fft_c2r<double><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out, out_row, add,
+                                                    add_scale, Nt, ncols, plan, lp, (const cx<double>*)tw,
+                                                    out_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch, int nb, const PtrBatch* dout,
+                        void* dh, int64_t dh_batch, int Nt, int Nd, const FftPlan& plan, const void* tw,
+                        double scale, hipStream_t st) {
+    const int lp = fft_log_cols(plan.N, r);
+    if (lp < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    dim3 grid(nblk(Nd, lp), nb), block(kFftThreads);
+    const size_t lds = fft_lds_bytes(plan.N, lp, r);
+    PtrBatch none{};
+    const PtrBatch& d = dout ? *dout : none;
+    if (r == Real::F32) {
+        if (dout)
+            k_dside<float, false><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,
+                                                            (cx<float>*)dh, dh_batch, Nt, Nd, plan, lp,
+                                                            (const cx<float>*)tw, (float)scale);
+        else
+            k_dside<float, true><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,
+                                                           (cx<float>*)dh, dh_batch, Nt, Nd, plan, lp,
+                                                           (const cx<float>*)tw, (float)scale);
+    } else {
+        if (dout)
+            k_dside<double, false><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,
+                                                             (cx<double>*)dh, dh_batch, Nt, Nd, plan, lp,
+                                                             (const cx<double>*)tw, scale);
+        else
+            k_dside<double, true><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,
+                                                            (cx<double>*)dh, dh_batch, Nt, Nd, plan, lp,
+                                                            (const cx<double>*)tw, scale);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace btoep

@@ -1,0 +1,72 @@
+// Host-side declarations shared by the btoep translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace btoep {
+
+// Mixed-radix factorisation of the half-length complex transform N (radices 2,3,4,5,7,8).
+constexpr int kMaxPass = 16;
+struct FftPlan {
+    int N;
+    int npass;
+    int radix[kMaxPass];
+};
+
+// Up to kMaxBatch right-hand-side base pointers, passed by value as a kernel argument.
+constexpr int kMaxBatch = 64;
+struct PtrBatch {
+    const void* p[kMaxBatch];
+};
+
+enum class Real { F32, F64 };
+enum class Stor { C128 = 0, C64 = 1, BF16 = 2 };
+
+// Threads per workgroup of every FFT kernel.
+constexpr int kFftThreads = 256;
+
+// Columns per FFT workgroup (power of two, log2) for a transform of half-length N in
+// real type `r`; 0 columns (returns -1) when N does not fit one workgroup.
+int fft_log_cols(int N, Real r);
+size_t fft_lds_bytes(int N, int logP, Real r);
+
+// ---- launchers (fft.hip) ------------------------------------------------------------
+// Forward real-to-complex transform of zero-padded columns.
+//   in  : batch b (b < nb) base in.p[b]; element (j, c) at [j * in_row + c], j < Nt, c < ncols
+//   out : complex, element (f, c) at out + b*out_batch + f*out_row + c, f <= N
+// Storage of `out` follows `os`; the compute precision is `r`.  Inputs of type `ir`.
+hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_row, int nb,
+                          void* out, int64_t out_row, int64_t out_batch, int Nt, int ncols,
+                          const FftPlan& plan, const void* tw, hipStream_t st);
+// Setup form: batch over sensor rows s with explicit strides (block column input).
+hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int64_t in_batch, int nb,
+                                  void* out, int64_t out_row, int64_t out_batch, int Nt, int ncols,
+                                  const FftPlan& plan, const void* tw64, hipStream_t st);
+// Inverse complex-to-real transform; keeps samples j < Nt:
+//   out[b][j][c] = out_scale * x_j  (+ add_scale * add[b][j][c] when add.p[0] != null)
+hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_batch, int nb,
+                          const PtrBatch& out, int64_t out_row, const PtrBatch& add, double add_scale,
+                          int Nt, int ncols, const FftPlan& plan, const void* tw, double out_scale,
+                          hipStream_t st);
+// Data side of F and H: sums split partial sums part[b][f][span][s] over spans, inverse
+// transforms along f, keeps j < Nt and scales by `scale`.  With `dout` given, writes the data
+// vector d[b][j][s]; otherwise (H) zero-pads and forward transforms again into dh[b][f][s].
+hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch, int nb,
+                        const PtrBatch* dout, void* dh, int64_t dh_batch, int Nt, int Nd,
+                        const FftPlan& plan, const void* tw, double scale, hipStream_t st);
+
+// ---- launchers (sbgemv.hip) ---------------------------------------------------------
+// Per-frequency products with the stored operator Fh[f][s][p] (row stride ldF, frequency
+// stride Nd*ldF).  N: part[b][f][span][s] = sum_{p in span} Fh[f][s][p] mh[b][f][p].
+// C: mo[b][f][p] = sum_s conj(Fh[f][s][p]) dh[b][f][s].
+int sbgemv_n_span(Stor st, int64_t Nm);
+hipError_t launch_sbgemv_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
+                           const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
+                           int nspan, int64_t part_batch, hipStream_t s);
+hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
+                           const void* dh, int64_t dh_batch, int nb, void* mo, int64_t ldv,
+                           int64_t mo_batch, hipStream_t s);
+
+}  // namespace btoep

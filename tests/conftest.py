@@ -8,3 +8,17 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(scope="session")
+def bt():
+    """The HIP binding; builds libbtoep.so only when no library is present."""
+    import paper_2407_13066_amd as pkg
+    from paper_2407_13066_amd import build
+    if not os.path.exists(pkg.LIB_PATH):
+        build.build()
+    pkg.load_library()
+    return pkg
