@@ -28,6 +28,7 @@ struct btoep_op_s {
     FftPlan plan{};
     void* tw64 = nullptr;  // exp(-2 pi i t / L), t < L, complex FP64
     void* tw32 = nullptr;  // same, complex FP32
+    bool gemm_enabled = true;  // MFMA kernels for several right-hand sides
     void* ws = nullptr;    // operator-owned workspace (used when the caller passes none)
     size_t ws_cap = 0;
     std::mutex mu;
@@ -213,6 +214,40 @@ hipError_t timed(btoep_op op, int kid, hipStream_t st, Fn&& fn) {
 const void* tw_of(const btoep_op op) { return op->vreal == Real::F64 ? op->tw64 : op->tw32; }
 Stor vstor(const btoep_op op) { return op->vreal == Real::F64 ? Stor::C128 : Stor::C64; }
 
+// Per-frequency products: one vector per launch row (GEMV kernels) for a single right-hand
+// side or FP64 storage; the MFMA kernels for nb >= 2 on FP32 / BF16 storage.
+bool use_gemm(const btoep_op op, int nb) { return nb >= 2 && op->stor != Stor::C128 && op->gemm_enabled; }
+
+hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part, int nspan, int64_t part_b,
+                  hipStream_t st) {
+    const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
+    if (use_gemm(op, nb))
+        return launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b,
+                               st);
+    return launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b, st);
+}
+
+hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, int64_t vh_b, hipStream_t st) {
+    const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
+    if (use_gemm(op, nb)) {
+        // right-hand-side groups small enough for the staged data spectra
+        int g = nb;
+        while (g > 1 && sbgemm_c_lds(g, Nd) > 64 * 1024) g = (g + 1) / 2;
+        for (int r0 = 0; r0 < nb; r0 += g) {
+            const int n = std::min(g, nb - r0);
+            hipError_t e = (n >= 2) ? launch_sbgemm_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
+                                                      (const char*)dh + (size_t)r0 * dh_b * 8, dh_b, n,
+                                                      (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st)
+                                    : launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
+                                                      (const char*)dh + (size_t)r0 * dh_b * 8, dh_b, n,
+                                                      (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st);
+}
+
 // One pipeline launch sequence over nb <= kMaxBatch right-hand sides.
 btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& in, const PtrBatch& out,
                        double noise_prec, double prior_prec, char* ws, hipStream_t st) {
@@ -232,8 +267,7 @@ btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& i
                                   st);
         }));
         BT_HIP(op, timed(op, K_SBGEMV_N, st, [&] {
-            return launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan,
-                                   part_b, st);
+            return prod_n(op, nb, vh, vh_b, part, nspan, part_b, st);
         }));
         if (which == BTOEP_APPLY_F) {
             BT_HIP(op, timed(op, K_DSIDE_F, st, [&] {
@@ -247,7 +281,7 @@ btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& i
                                 noise_prec * inv_n, st);
         }));
         BT_HIP(op, timed(op, K_SBGEMV_C, st, [&] {
-            return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st);
+            return prod_c(op, nb, dh, dh_b, vh, vh_b, st);
         }));
         BT_HIP(op, timed(op, K_C2R_M, st, [&] {
             return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, in, prior_prec, Nt, Nm, op->plan, tw,
@@ -260,7 +294,7 @@ btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& i
         return launch_fft_r2c(op->vreal, op->vreal, vstor(op), in, Nd, nb, dh, op->Nd, dh_b, Nt, Nd, op->plan, tw, st);
     }));
     BT_HIP(op, timed(op, K_SBGEMV_C, st, [&] {
-        return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st);
+        return prod_c(op, nb, dh, dh_b, vh, vh_b, st);
     }));
     BT_HIP(op, timed(op, K_C2R_M, st, [&] {
         return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, none, 0.0, Nt, Nm, op->plan, tw, inv_n, st);

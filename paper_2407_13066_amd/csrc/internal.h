@@ -69,4 +69,16 @@ hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
                            const void* dh, int64_t dh_batch, int nb, void* mo, int64_t ldv,
                            int64_t mo_batch, hipStream_t s);
 
+// ---- launchers (sbgemm.hip): k >= 2 right-hand sides on the matrix cores ----------------
+// Same operands and outputs as the single-vector launchers above, for nb right-hand sides in
+// one launch (FP32 or BF16 storage only).  sbgemm_c needs sbgemm_c_lds(nb, Nd) <= 64 KB.
+int sbgemm_n_span(int64_t Nm);
+size_t sbgemm_c_lds(int nb, int Nd);
+hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
+                           const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
+                           int nspan, int64_t part_batch, hipStream_t s);
+hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
+                           const void* dh, int64_t dh_batch, int nb, void* mo, int64_t ldv,
+                           int64_t mo_batch, hipStream_t s);
+
 }  // namespace btoep

@@ -1,0 +1,408 @@
+// Multi-right-hand-side per-frequency products on the matrix cores (MFMA).
+//
+// With k right-hand sides stacked, the per-frequency matrix-vector product of the paper's
+// "apply_matrix" step (section 3.3) becomes a matrix-matrix product per frequency, so the
+// stored operator is streamed once for all k vectors instead of k times.  A complex
+// product is run as one real GEMM: with the operator row read as interleaved (re, im)
+// pairs along K, the vector side is expanded on the fly to
+//      [ Re m  Im m ]                      (rows: re / im part of the operator entry,
+//      [-Im m  Re m ]                       columns: re / im part of the result)
+// so that a real MFMA accumulates Re(F m) and Im(F m) directly.  The adjoint uses the
+// conjugate-transposed pattern [[Re d, Im d], [Im d, -Re d]] (eq. AdjointFFTMatvec).
+//
+//   N (for F):  C_f (Nd x 2k) += Fh_f (Nd x 2Nm) B_f (2Nm x 2k), split over column spans
+//               (partial sums part[r][f][span][s], summed in order by the data-side kernel).
+//               A workgroup keeps the whole Nd x 2k accumulator of its span in registers
+//               and streams the right-hand sides through LDS in chunks of 64 columns.
+//   C (for F^T): O_f^T (2k x Nm) = D_f^T (2k x 2Nd) Fh_f (2Nd x Nm): the operator is the
+//               B operand, lanes own output columns p, so each result row of 16 p values
+//               is stored as one contiguous run; no reduction across workgroups.
+//
+// FP32 storage uses v_mfma_f32_16x16x4_f32; BF16 storage uses v_mfma_f32_16x16x32_bf16
+// with the FP32 vector operand split into a BF16 high part and a BF16 remainder (two
+// MFMAs), so the vector keeps ~16 significant bits and the result error is dominated by
+// the BF16 rounding of the stored operator.  Accumulation is FP32 in both.
+//
+// MFMA 16x16 operand layout used (lane l of 64, g = l / 16, i = l % 16):
+//   A (16 x K): lane holds row i, K group g;  B (K x 16): lane holds column i, K group g;
+//   C (16 x 16): lane holds C[4 g + v][i], v = 0..3.
+// Any fixed assignment of K indices to (group, item) is valid as long as A and B agree.
+#include "common.h"
+#include "internal.h"
+
+namespace btoep {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmThreads = 256;
+// complex columns of the vector side staged per LDS chunk (N direction): 64, or 32 for the
+// widest tile so that two chunk buffers stay within 64 KB of LDS
+template <int NT>
+struct Chunk {
+    static constexpr int value = NT >= 8 ? 32 : 64;
+};
+
+__device__ __forceinline__ f4v mfma_f32(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma_bf16(u32x4 a, u32x4 b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0,
+                                                   0, 0);
+}
+
+// (re, im) of a float complex as bf16 high parts and bf16 remainders, packed re | im << 16.
+__device__ __forceinline__ void split_bf16(float re, float im, uint32_t& hi, uint32_t& lo) {
+    const uint32_t rh = f32_to_bf16_rne(re), ih = f32_to_bf16_rne(im);
+    const float rr = re - __uint_as_float(rh << 16), ir = im - __uint_as_float(ih << 16);
+    hi = rh | (ih << 16);
+    lo = f32_to_bf16_rne(rr) | (f32_to_bf16_rne(ir) << 16);
+}
+// From a packed bf16 pair (re | im << 16): (re, -im) and (im, re).
+__device__ __forceinline__ uint32_t bf_re_negim(uint32_t x) { return x ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t bf_im_re(uint32_t x) { return (x >> 16) | (x << 16); }
+// (im, -re) for the adjoint pattern.
+__device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) | (x << 16)) ^ 0x80000000u; }
+
+// =========================================================================================
+// N direction.  Grid (nspan, nfreq); 4 waves; wave w owns row tiles 2w, 2w+1 of each group
+// of 128 rows; NT tiles of 16 real result columns (8 right-hand sides each).
+// LDS: two chunk buffers of nb x kChunk vector entries (row stride kChunk + 2).
+template <bool BF, int NT, int kChunk = Chunk<NT>::value>
+__global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
+                                                           const cx<float>* __restrict__ mh, int64_t ldv,
+                                                           int64_t mh_batch, int nb, cx<float>* __restrict__ part,
+                                                           int CS, int nspan, int64_t part_batch) {
+    constexpr int LDR = kChunk + 2;  // row stride (entries) of a staged chunk
+    // entry = float complex (FP32 path) or (hi, lo) packed bf16 pairs (BF16 path): 8 bytes
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint2* buf = reinterpret_cast<uint2*>(smem_raw);  // [2][NT*8][LDR]
+    const int span = blockIdx.x, f = blockIdx.y;
+    const int col0 = span * CS;
+    const int ncol = min(CS, Nm - col0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nchunk = (ncol + kChunk - 1) / kChunk;
+    const int rows_per_buf = NT * 8;
+
+    auto stage = [&](int c, int which) {
+        uint2* dst = buf + (size_t)which * rows_per_buf * LDR;
+        const int cbase = col0 + c * kChunk;
+        for (int e = threadIdx.x; e < rows_per_buf * kChunk; e += kGemmThreads) {
+            const int r = e / kChunk, q = e % kChunk;
+            float re = 0.f, im = 0.f;
+            if (r < nb && cbase + q < col0 + ncol) {
+                const cx<float> v = mh[(int64_t)r * mh_batch + (int64_t)f * ldv + cbase + q];
+                re = v.re;
+                im = v.im;
+            }
+            uint2 out;
+            if (BF) {
+                split_bf16(re, im, out.x, out.y);
+            } else {
+                out.x = __float_as_uint(re);
+                out.y = __float_as_uint(im);
+            }
+            dst[r * LDR + q] = out;
+        }
+    };
+
+    for (int rg = 0; rg < Nd; rg += 128) {
+        const int rt0 = rg + wave * 32;  // first row of this wave's two 16-row tiles
+        const bool t0 = rt0 < Nd, t1 = rt0 + 16 < Nd;
+        const int s0 = min(rt0 + li, Nd - 1), s1 = min(rt0 + 16 + li, Nd - 1);
+        const char* F0 = (const char*)Fh_ + ((int64_t)f * Nd + s0) * ldF * (BF ? 4 : 8);
+        const char* F1 = (const char*)Fh_ + ((int64_t)f * Nd + s1) * ldF * (BF ? 4 : 8);
+        f4v acc[2][NT];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
+
+        __syncthreads();
+        stage(0, 0);
+        for (int c = 0; c < nchunk; ++c) {
+            __syncthreads();
+            if (c + 1 < nchunk) stage(c + 1, (c + 1) & 1);
+            const uint2* B = buf + (size_t)(c & 1) * rows_per_buf * LDR;
+            const int cb = col0 + c * kChunk;  // first complex column of the chunk
+            if (t0) {
+                // K step = 16 complex columns; lane group lg covers columns 4 lg .. 4 lg + 3
+#pragma unroll
+                for (int ks = 0; ks < kChunk / 16; ++ks) {
+                    const int q0 = ks * 16 + lg * 4;       // column within the chunk
+                    const int64_t col = cb + q0;           // operator column
+                    const bool in = (col < col0 + ncol);   // whole 4-column group lies past the end otherwise
+                    if (!BF) {
+                        float a0[8], a1[8];
+                        if (in) {
+                            const u32x4* p0 = (const u32x4*)(F0 + col * 8);
+                            const u32x4 w0 = p0[0], w1 = p0[1];
+                            const u32x4* p1 = (const u32x4*)(F1 + col * 8);
+                            const u32x4 x0 = p1[0], x1 = p1[1];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                a0[e] = __uint_as_float(w0[e]);
+                                a0[4 + e] = __uint_as_float(w1[e]);
+                                a1[e] = __uint_as_float(x0[e]);
+                                a1[4 + e] = __uint_as_float(x1[e]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) a0[e] = a1[e] = 0.f;
+                        }
+#pragma unroll
+                        for (int n = 0; n < NT; ++n) {
+                            const int r = n * 8 + (li >> 1);
+                            const bool imcol = li & 1;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const uint2 mv = B[r * LDR + q0 + q];
+                                const float mre = __uint_as_float(mv.x), mim = __uint_as_float(mv.y);
+                                // K = (column q, part c): c = 0 real, c = 1 imaginary part of F
+                                const float b0 = imcol ? mim : mre;   // pairs with Re F
+                                const float b1 = imcol ? mre : -mim;  // pairs with Im F
+                                acc[0][n] = mfma_f32(a0[2 * q], b0, acc[0][n]);
+                                acc[0][n] = mfma_f32(a0[2 * q + 1], b1, acc[0][n]);
+                                if (t1) {
+                                    acc[1][n] = mfma_f32(a1[2 * q], b0, acc[1][n]);
+                                    acc[1][n] = mfma_f32(a1[2 * q + 1], b1, acc[1][n]);
+                                }
+                            }
+                        }
+                    } else {
+                        u32x4 a0 = {0u, 0u, 0u, 0u}, a1 = {0u, 0u, 0u, 0u};
+                        if (in) {
+                            a0 = *(const u32x4*)(F0 + col * 4);
+                            a1 = *(const u32x4*)(F1 + col * 4);
+                        }
+#pragma unroll
+                        for (int n = 0; n < NT; ++n) {
+                            const int r = n * 8 + (li >> 1);
+                            const bool imcol = li & 1;
+                            u32x4 bh, bl;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const uint2 mv = B[r * LDR + q0 + q];
+                                bh[q] = imcol ? bf_im_re(mv.x) : bf_re_negim(mv.x);
+                                bl[q] = imcol ? bf_im_re(mv.y) : bf_re_negim(mv.y);
+                            }
+                            acc[0][n] = mfma_bf16(a0, bh, acc[0][n]);
+                            acc[0][n] = mfma_bf16(a0, bl, acc[0][n]);
+                            if (t1) {
+                                acc[1][n] = mfma_bf16(a1, bh, acc[1][n]);
+                                acc[1][n] = mfma_bf16(a1, bl, acc[1][n]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // C[4 lg + v][li]: row s = rt0 + 16 a + 4 lg + v, column li -> rhs n*8 + li/2, part li&1
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int r = n * 8 + (li >> 1);
+                if (r >= nb) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int s = rt0 + 16 * a + 4 * lg + v;
+                    if (s < Nd) {
+                        float* o = reinterpret_cast<float*>(part + (int64_t)r * part_batch +
+                                                            ((int64_t)f * nspan + span) * Nd + s);
+                        o[li & 1] = acc[a][n][v];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// =========================================================================================
+// C direction.  Grid (ceil(Nm / 128), nfreq); 4 waves; wave w owns result columns
+// p0 = 128 blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
+// result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are
+// staged in LDS once (as the A operand pattern's source).
+template <bool BF, int NT>
+__global__ __launch_bounds__(kGemmThreads) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
+                                                           const cx<float>* __restrict__ dh, int64_t dh_batch, int nb,
+                                                           cx<float>* __restrict__ mo, int64_t ldv, int64_t mo_batch) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint2* dsh = reinterpret_cast<uint2*>(smem_raw);  // [NT*8][Ndp]: float complex or (hi, lo) bf16 pairs
+    const int Ndp = (Nd + 15) & ~15;
+    const int f = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    for (int e = threadIdx.x; e < NT * 8 * Ndp; e += kGemmThreads) {
+        const int r = e / Ndp, s = e % Ndp;
+        float re = 0.f, im = 0.f;
+        if (r < nb && s < Nd) {
+            const cx<float> v = dh[(int64_t)r * dh_batch + (int64_t)f * Nd + s];
+            re = v.re;
+            im = v.im;
+        }
+        uint2 o;
+        if (BF) {
+            split_bf16(re, im, o.x, o.y);
+        } else {
+            o.x = __float_as_uint(re);
+            o.y = __float_as_uint(im);
+        }
+        dsh[e] = o;
+    }
+    __syncthreads();
+
+    const int pbase = blockIdx.x * 128 + wave * 32;
+    const int pc[2] = {min(pbase + li, Nm - 1), min(pbase + 16 + li, Nm - 1)};
+    const bool tile1 = pbase + 16 < Nm;
+    if (pbase >= Nm) return;
+    f4v acc[2][NT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t frow = (int64_t)f * Nd;
+    if (!BF) {
+        const cx<float>* Fh = (const cx<float>*)Fh_;
+        // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs
+        for (int s0 = 0; s0 < Nd; s0 += 4) {
+            const int s = s0 + lg;
+            const bool sv = s < Nd;
+            const int sc = sv ? s : Nd - 1;
+            cx<float> b[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                b[a] = Fh[(frow + sc) * ldF + pc[a]];
+                if (!sv) b[a] = cx<float>{0.f, 0.f};
+            }
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
+                const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
+                const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
+                const bool imrow = li & 1;
+                const float a0 = imrow ? dim : dre;   // pairs with Re F
+                const float a1 = imrow ? -dre : dim;  // pairs with Im F
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
+                    acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
+                }
+            }
+        }
+    } else {
+        const uint32_t* Fh = (const uint32_t*)Fh_;
+        // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im)
+        for (int s0 = 0; s0 < Nd; s0 += 16) {
+            u32x4 b[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int s = s0 + 4 * lg + q;
+                    b[a][q] = (s < Nd) ? Fh[(frow + s) * ldF + pc[a]] : 0u;
+                }
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int r = n * 8 + (li >> 1);
+                const bool imrow = li & 1;
+                u32x4 ah, al;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int s = s0 + 4 * lg + q;  // < Ndp; zero-filled past Nd
+                    const uint2 dv = dsh[r * Ndp + s];
+                    // K items (re F, im F) pair with (Re d, Im d) for the real row, (Im d, -Re d) for the imaginary row
+                    ah[q] = imrow ? bf_im_negre(dv.x) : dv.x;
+                    al[q] = imrow ? bf_im_negre(dv.y) : dv.y;
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    acc[a][n] = mfma_bf16(ah, b[a], acc[a][n]);
+                    acc[a][n] = mfma_bf16(al, b[a], acc[a][n]);
+                }
+            }
+        }
+    }
+    // C[4 lg + v][li]: result row 4 lg + v -> rhs n*8 + 2 lg + v/2, part v&1; column p = tile + li
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int p = pbase + 16 * a + li;
+        if (p >= Nm || (a == 1 && !tile1)) continue;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = n * 8 + 2 * lg + h;
+                if (r < nb)
+                    mo[(int64_t)r * mo_batch + (int64_t)f * ldv + p] = cx<float>{acc[a][n][2 * h], acc[a][n][2 * h + 1]};
+            }
+        }
+    }
+}
+
+// =========================================================================================
+int sbgemm_n_span(int64_t Nm) {
+    // same spans as the single-vector kernel: 4096 columns, or one span rounded to 64 columns
+    const int64_t cs = 4096;
+    const int64_t need = ((Nm + 63) / 64) * 64;
+    return (int)(cs < need ? cs : need);
+}
+
+size_t sbgemm_c_lds(int nb, int Nd) {
+    const int NT = nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8));
+    return (size_t)NT * 8 * ((Nd + 15) & ~15) * 8;
+}
+
+static int nt_of(int nb) { return nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8)); }
+
+hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
+                           int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
+                           hipStream_t s) {
+    if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+    const int CS = sbgemm_n_span(Nm);
+    if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
+    const int NT = nt_of(nb);
+    const int ch = NT >= 8 ? Chunk<8>::value : Chunk<1>::value;
+    const size_t lds = (size_t)2 * NT * 8 * (ch + 2) * 8;
+    dim3 grid(nspan, nfreq), block(kGemmThreads);
+    const cx<float>* m = (const cx<float>*)mh;
+    cx<float>* p = (cx<float>*)part;
+#define BT_GN(BFV, NTV) \
+    k_sbgemm_n<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, part_batch)
+    const bool bf = st == Stor::BF16;
+    switch (NT) {
+        case 1: if (bf) BT_GN(true, 1); else BT_GN(false, 1); break;
+        case 2: if (bf) BT_GN(true, 2); else BT_GN(false, 2); break;
+        case 4: if (bf) BT_GN(true, 4); else BT_GN(false, 4); break;
+        default: if (bf) BT_GN(true, 8); else BT_GN(false, 8); break;
+    }
+#undef BT_GN
+    return hipGetLastError();
+}
+
+hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* dh,
+                           int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s) {
+    if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+    const int NT = nt_of(nb);
+    const size_t lds = sbgemm_c_lds(nb, Nd);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((Nm + 127) / 128), nfreq), block(kGemmThreads);
+    const cx<float>* d = (const cx<float>*)dh;
+    cx<float>* o = (cx<float>*)mo;
+#define BT_GC(BFV, NTV) \
+    k_sbgemm_c<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch)
+    const bool bf = st == Stor::BF16;
+    switch (NT) {
+        case 1: if (bf) BT_GC(true, 1); else BT_GC(false, 1); break;
+        case 2: if (bf) BT_GC(true, 2); else BT_GC(false, 2); break;
+        case 4: if (bf) BT_GC(true, 4); else BT_GC(false, 4); break;
+        default: if (bf) BT_GC(true, 8); else BT_GC(false, 8); break;
+    }
+#undef BT_GC
+    return hipGetLastError();
+}
+
+}  // namespace btoep

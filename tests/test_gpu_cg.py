@@ -1,0 +1,125 @@
+"""CG on H x = b through the C-ABI (needs an MI355X).
+
+Pins: the dense solve of the assembled H on a tiny problem; the true residual recomputed by
+the FP64 oracle's H; the same solution from plain FP64 CG and from low-precision inner CG
+with FP64 iterative refinement.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests import pins
+from tests.gpu_helpers import make, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def solve(bt, lo, hi, b, noise_prec, prior_prec, **kw):
+    bd = to_dev(b, torch.float64)
+    x = torch.zeros_like(bd)
+    st, res = bt.btoep_cg_solve(lo, hi, bd, x, noise_prec, prior_prec, **kw)
+    torch.cuda.synchronize()
+    return st, res, x.cpu().numpy()
+
+
+def test_cg_tiny_matches_dense_solve(bt):
+    rng = np.random.default_rng(21)
+    Nt, Nd, Nm = 6, 2, 5
+    blocks = rng.standard_normal((Nt, Nd, Nm))
+    b = rng.standard_normal((Nt, Nm))
+    noise_prec, prior_prec = 4.0, 0.1
+    A = pins.dense_matrix(blocks)
+    Hd = noise_prec * A.T @ A + prior_prec * np.eye(A.shape[1])
+    x_ref = np.linalg.solve(Hd, b.ravel()).reshape(Nt, Nm)
+    op = make(bt, blocks, "f64")
+    st, res, x = solve(bt, op, None, b[None], noise_prec, prior_prec, rtol=1e-13, inner_rtol=1e-14,
+                       max_inner=200)
+    assert st == 0 and res[0]["converged"], res
+    assert res[0]["rel_residual"] <= 1e-13
+    assert oracle.rel_l2(x[0], x_ref) <= 1e-10
+
+
+# Refinement contracts when the low-precision operator's perturbation of H, seen through
+# the smallest eigenvalue prior_prec, stays below one: roughly eps^2 * lambda_max / prior_prec < 1
+# with eps the relative error of the stored operator (FP32 ~3e-8, BF16 ~2e-3) and
+# lambda_max ~ noise_prec * ||F||^2.  The FP32 case uses the inverse-problem scalars
+# (sigma = 1e-2, alpha = 1e-3, lambda_max / alpha ~ 1e10); BF16 needs a milder prior.
+@pytest.mark.parametrize("lo_storage,sigma,alpha,inner_rtol", [("f32", 1e-2, 1e-3, 1e-5),
+                                                                ("bf16", 1.0, 10.0, 1e-2)])
+def test_refinement_reaches_fp64_accuracy(bt, lo_storage, sigma, alpha, inner_rtol):
+    """Low-precision inner CG inside FP64 refinement meets 1e-8 on the true residual and
+    agrees with all-FP64 CG; checked with the oracle's H."""
+    rng = np.random.default_rng(22)
+    Nt, Nd, Nm, k = 48, 6, 700, 2
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / (Nt / 7))[:, None, None]
+    m_true = rng.standard_normal((k, Nt, Nm))
+    dobs = oracle.apply_F(blocks, m_true) + sigma * rng.standard_normal((k, Nt, Nd))
+    noise_prec = sigma ** -2
+    b = noise_prec * oracle.apply_FT(blocks, dobs)
+    hi = make(bt, blocks, "f64")
+    lo = make(bt, blocks, lo_storage)
+    st, res, x = solve(bt, lo, hi, b, noise_prec, alpha, rtol=1e-8, inner_rtol=inner_rtol)
+    print(lo_storage, res, flush=True)
+    assert st == 0, res
+    st64, res64, x64 = solve(bt, hi, None, b, noise_prec, alpha, rtol=1e-8, inner_rtol=1e-9)
+    assert st64 == 0, res64
+    for r in range(k):
+        Hx = oracle.apply_H(blocks, x[r], noise_prec, alpha)
+        assert np.linalg.norm(b[r] - Hx) / np.linalg.norm(b[r]) <= 1.01e-8
+        Hx64 = oracle.apply_H(blocks, x64[r], noise_prec, alpha)
+        assert np.linalg.norm(b[r] - Hx64) / np.linalg.norm(b[r]) <= 1.01e-8
+        # data-space agreement of the two solutions (null-space components are not controlled)
+        Fd = oracle.apply_F(blocks, x[r] - x64[r])
+        assert np.linalg.norm(Fd) <= 1e-6 * np.linalg.norm(oracle.apply_F(blocks, x64[r]))
+
+
+def test_cg_reports_not_converged(bt):
+    rng = np.random.default_rng(23)
+    blocks = rng.standard_normal((16, 4, 64))
+    b = rng.standard_normal((1, 16, 64))
+    op = make(bt, blocks, "f64")
+    st, res, x = solve(bt, op, None, b, 1e4, 1e-3, rtol=1e-14, max_outer=1, max_inner=2, inner_rtol=1e-14)
+    assert st == bt.BTOEP_ERR_NOT_CONVERGED
+    assert not res[0]["converged"] and res[0]["rel_residual"] > 1e-14
+
+
+def test_cg_inputs_validated(bt):
+    blocks = np.ones((8, 2, 3))
+    lo = make(bt, blocks, "f32")
+    b = torch.zeros((1, 8, 3), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_cg_solve(lo, None, b, x, 1.0, 1.0)   # an FP32 operator needs an FP64 partner
+    other = make(bt, np.ones((8, 2, 4)), "f64")
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_cg_solve(lo, other, b, x, 1.0, 1.0)  # shapes differ
+
+
+@pytest.mark.timeout(900)
+def test_cg_workload_nt256_nd64_nm16384(bt):
+    """H = sigma^-2 F^T F + alpha I, sigma = 1e-2, alpha = 1e-3, Nt=256, Nd=64, Nm=16384,
+    d = F m_true + N(0, sigma^2), b = sigma^-2 F^T d: FP32 inner CG with FP64 refinement
+    and plain FP64 CG both reach 1e-8, checked with the oracle's H."""
+    w = synth.WORKLOADS["cg-nt256-nd64-nm16384"]
+    Nt, Nd, Nm, tau = w["Nt"], w["Nd"], w["Nm"], w["tau"]
+    print("case cg workload", flush=True)
+    blocks = synth.blocks(Nt, Nd, Nm, tau)
+    m_true = synth.vectors(1, Nt, Nm, synth.STREAM_MTRUE)[0]
+    noise = synth.vectors(1, Nt, Nd, synth.STREAM_NOISE)[0]
+    sigma, alpha = w["sigma"], w["alpha"]
+    dobs = oracle.apply_F(blocks, m_true) + sigma * noise
+    noise_prec = sigma ** -2
+    b = noise_prec * oracle.apply_FT(blocks, dobs)
+    hi = make(bt, blocks, "f64")
+    lo = make(bt, blocks, "f32")
+    st, res, x = solve(bt, lo, hi, b[None], noise_prec, alpha, rtol=w["rtol"], inner_rtol=1e-5)
+    print("refined f32:", res, flush=True)
+    assert st == 0
+    st64, res64, x64 = solve(bt, hi, None, b[None], noise_prec, alpha, rtol=w["rtol"], inner_rtol=1e-9)
+    print("fp64:", res64, flush=True)
+    assert st64 == 0
+    for xx in (x[0], x64[0]):
+        Hx = oracle.apply_H(blocks, xx, noise_prec, alpha)
+        assert np.linalg.norm(b - Hx) / np.linalg.norm(b) <= 1.01e-8

@@ -1,0 +1,97 @@
+"""Full-size parity on the benchmarked operator shape (needs an MI355X and ~60 GB of host memory).
+
+Workload: Nt=420, Nd=100, Nm=65536, F_k = N(0,1) exp(-k/60), FP32-complex storage (22 GB),
+launched exactly as the benchmark launches it.  Full output vectors are compared with the
+FP64 oracle (lag-outer block products); the tolerance is 1e-5 relative l2 for FP32 storage
+and 3e-3 for BF16.  A second check needs no oracle: a rank-one geometric operator
+F_k = rho^k u v^T with constant input blocks has a closed-form output at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests import pins
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
+
+W = synth.WORKLOADS["fp32-nt420-nd100-nm65536"]
+Nt, Nd, Nm, TAU = W["Nt"], W["Nd"], W["Nm"], W["tau"]
+
+
+@pytest.fixture(scope="module")
+def blocks():
+    print("case full-size: generating blocks", flush=True)
+    return synth.blocks(Nt, Nd, Nm, TAU)
+
+
+@pytest.fixture(scope="module")
+def op32(bt, blocks):
+    print("case full-size: creating FP32 operator", flush=True)
+    return bt.btoep_create(blocks, "f32")
+
+
+def test_closed_form_rank_one_at_full_size(bt):
+    """F_k = rho^k u v^T, m_j = w, d_i = z: (F m)_i = u (v.w)(1-rho^{i+1})/(1-rho),
+    (F^T d)_j = v (u.z)(1-rho^{Nt-j})/(1-rho) -- no oracle involved."""
+    print("case full-size closed form", flush=True)
+    rng = np.random.default_rng(31)
+    rho = 0.985
+    u = rng.standard_normal(Nd)
+    v = rng.standard_normal(Nm)
+    w = rng.standard_normal(Nm)
+    z = rng.standard_normal(Nd)
+    k = torch.arange(Nt, dtype=torch.float64, device="cuda")
+    uv = torch.outer(torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda())
+    dev_blocks = (rho ** k)[:, None, None] * uv[None]
+    op = bt.btoep_create(dev_blocks, "f32")
+    del dev_blocks, uv
+    torch.cuda.empty_cache()
+    m = torch.from_numpy(np.tile(w, (Nt, 1))).cuda().float()
+    d = torch.from_numpy(np.tile(z, (Nt, 1))).cuda().float()
+    Fm = bt.btoep_apply_F(op, m).double().cpu().numpy()
+    FTd = bt.btoep_apply_FT(op, d).double().cpu().numpy()
+    w32 = m[0].double().cpu().numpy()
+    z32 = d[0].double().cpu().numpy()
+    assert pins.rel(Fm, pins.closed_form_F(u, v, w32, rho, Nt)) <= 1e-5
+    assert pins.rel(FTd, pins.closed_form_FT(u, v, z32, rho, Nt)) <= 1e-5
+    op.destroy()
+
+
+def test_full_vectors_F_FT_H(bt, blocks, op32):
+    print("case full-size F/FT/H parity", flush=True)
+    m = synth.vectors(1, Nt, Nm, synth.STREAM_M, dtype=np.float32)[0]
+    d = synth.vectors(1, Nt, Nd, synth.STREAM_D, dtype=np.float32)[0]
+    md = torch.from_numpy(m).cuda()
+    dd = torch.from_numpy(d).cuda()
+    Fm = bt.btoep_apply_F(op32, md).double().cpu().numpy()
+    FTd = bt.btoep_apply_FT(op32, dd).double().cpu().numpy()
+    Hm = bt.btoep_apply_H(op32, md, 1.0, 1.0).double().cpu().numpy()
+    m64, d64 = m.astype(np.float64), d.astype(np.float64)
+    Fm_ref = oracle.apply_F(blocks, m64)
+    e_F = oracle.rel_l2(Fm, Fm_ref)
+    e_FT = oracle.rel_l2(FTd, oracle.apply_FT(blocks, d64))
+    e_H = oracle.rel_l2(Hm, oracle.apply_FT(blocks, Fm_ref) + m64)
+    print("rel l2: F %.2e  FT %.2e  H %.2e" % (e_F, e_FT, e_H), flush=True)
+    assert e_F <= 1e-5 and e_FT <= 1e-5 and e_H <= 1e-5
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+def test_multi_rhs_full_size(bt, blocks, op32, storage, tol):
+    """k = 8 right-hand sides at full size; every column against the oracle."""
+    print("case full-size k=8", storage, flush=True)
+    op = op32 if storage == "f32" else bt.btoep_create(blocks, "bf16")
+    k = 8
+    M = synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=np.float32)
+    Md = torch.from_numpy(M).cuda()
+    FM = bt.btoep_apply_F(op, Md).double().cpu().numpy()
+    HM = bt.btoep_apply_H(op, Md, 1.0, 1.0).double().cpu().numpy()
+    M64 = M.astype(np.float64)
+    FM_ref = oracle.apply_F(blocks, M64)
+    HM_ref = oracle.apply_FT(blocks, FM_ref) + M64
+    for r in range(k):
+        assert oracle.rel_l2(FM[r], FM_ref[r]) <= tol
+        assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol
+    if op is not op32:
+        op.destroy()

@@ -78,9 +78,10 @@ def test_ragged_shapes(bt, shape, storage):
     assert oracle.rel_l2(Hm, oracle.apply_H(blocks, m, 2.0, 0.5)) <= tol
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_multi_rhs_and_pointer_batches(bt, storage):
-    """k right-hand sides stacked, and the pointer-array form, equal solo runs (bitwise)."""
+    """k right-hand sides stacked equal the pointer-array form bitwise, and solo runs within
+    the tolerance (bitwise for FP64 storage, where every k uses the same kernels)."""
     rng = np.random.default_rng(11)
     Nt, Nd, Nm, k = 24, 6, 700, 5
     blocks = rng.standard_normal((Nt, Nd, Nm))
@@ -95,14 +96,76 @@ def test_multi_rhs_and_pointer_batches(bt, storage):
     bt.btoep_apply_batched(op, "H", [M[r] for r in range(k)], outs, 3.0, 0.25)
     outs_f = [torch.empty((Nt, Nd), dtype=vt, device="cuda") for _ in range(k)]
     bt.btoep_apply_batched(op, "F", [M[r] for r in range(k)], outs_f)
+    outs_t = [torch.empty((Nt, Nm), dtype=vt, device="cuda") for _ in range(k)]
+    bt.btoep_apply_batched(op, "FT", [D[r] for r in range(k)], outs_t)
+    tol = TOL[storage]
     for r in range(k):
-        assert torch.equal(bt.btoep_apply_F(op, M[r]), FM[r])
-        assert torch.equal(bt.btoep_apply_FT(op, D[r]), FTD[r])
-        assert torch.equal(bt.btoep_apply_H(op, M[r], 3.0, 0.25), HM[r])
         assert torch.equal(outs[r], HM[r])
         assert torch.equal(outs_f[r], FM[r])
+        assert torch.equal(outs_t[r], FTD[r])
+        solo = [bt.btoep_apply_F(op, M[r]), bt.btoep_apply_FT(op, D[r]), bt.btoep_apply_H(op, M[r], 3.0, 0.25)]
+        for a, b in zip(solo, (FM[r], FTD[r], HM[r])):
+            if storage == "f64":
+                assert torch.equal(a, b)
+            else:
+                assert oracle.rel_l2(a.double().cpu().numpy(), b.double().cpu().numpy()) <= tol
     Mn = M.double().cpu().numpy()
-    assert oracle.rel_l2(FM.double().cpu().numpy(), oracle.apply_F(blocks, Mn)) <= TOL[storage]
+    Dn = D.double().cpu().numpy()
+    FM_ref = oracle.apply_F(blocks, Mn)
+    FTD_ref = oracle.apply_FT(blocks, Dn)
+    HM_ref = oracle.apply_H(blocks, Mn, 3.0, 0.25)
+    for r in range(k):
+        assert oracle.rel_l2(FM[r].double().cpu().numpy(), FM_ref[r]) <= tol
+        assert oracle.rel_l2(FTD[r].double().cpu().numpy(), FTD_ref[r]) <= tol
+        assert oracle.rel_l2(HM[r].double().cpu().numpy(), HM_ref[r]) <= tol
+
+
+# k crossing every tile width of the matrix-core kernels (8 right-hand sides per tile),
+# with ragged Nm, Nd above one 128-row group, and Nd large enough that the adjoint's staged
+# data spectra are split into groups
+MULTI = [((13, 7, 1000), 2), ((13, 7, 1000), 9), ((64, 100, 4099), 8), ((64, 100, 4099), 17),
+         ((17, 130, 257), 33), ((20, 200, 700), 64), ((9, 3, 130), 64)]
+
+
+@pytest.mark.parametrize("shape,k", MULTI)
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_multi_rhs_matrix_cores(bt, shape, k, storage):
+    Nt, Nd, Nm = shape
+    print("case multi", shape, k, storage, flush=True)
+    rng = np.random.default_rng(Nt + 7 * Nd + Nm + k)
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / max(Nt / 7, 1))[:, None, None]
+    op = make(bt, blocks, storage)
+    M = rng.standard_normal((k, Nt, Nm)).astype(np.float32)
+    D = rng.standard_normal((k, Nt, Nd)).astype(np.float32)
+    Md, Dd = to_dev(M, torch.float32), to_dev(D, torch.float32)
+    FM = bt.btoep_apply_F(op, Md).double().cpu().numpy()
+    FTD = bt.btoep_apply_FT(op, Dd).double().cpu().numpy()
+    HM = bt.btoep_apply_H(op, Md, 1.5, 0.75).double().cpu().numpy()
+    M64, D64 = M.astype(np.float64), D.astype(np.float64)
+    FM_ref = oracle.apply_F(blocks, M64)
+    FTD_ref = oracle.apply_FT(blocks, D64)
+    HM_ref = oracle.apply_H(blocks, M64, 1.5, 0.75)
+    tol = TOL[storage]
+    for r in range(k):
+        assert oracle.rel_l2(FM[r], FM_ref[r]) <= tol, ("F", r)
+        assert oracle.rel_l2(FTD[r], FTD_ref[r]) <= tol, ("FT", r)
+        assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol, ("H", r)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_matrix_core_results_are_batch_invariant(bt, storage):
+    """A right-hand side gives bitwise the same result in any batch of k >= 2 and at any position."""
+    rng = np.random.default_rng(41)
+    Nt, Nd, Nm = 30, 20, 1500
+    op = make(bt, rng.standard_normal((Nt, Nd, Nm)), storage)
+    V = to_dev(rng.standard_normal((12, Nt, Nm)), torch.float32)
+    big = bt.btoep_apply_H(op, V, 2.0, 0.5)
+    small = bt.btoep_apply_H(op, V[[7, 3, 9]].contiguous(), 2.0, 0.5)
+    for a, b in zip((7, 3, 9), range(3)):
+        assert torch.equal(big[a], small[b])
+    Fb = bt.btoep_apply_F(op, V)
+    Fs = bt.btoep_apply_F(op, V[[11, 0]].contiguous())
+    assert torch.equal(Fb[11], Fs[0]) and torch.equal(Fb[0], Fs[1])
 
 
 def test_repeat_calls_are_bitwise_identical(bt):
