@@ -166,6 +166,26 @@ btoep_status btoep_cg_solve(btoep_op op_lo, btoep_op op_hi, int64_t k, double no
                             void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Autotuning: times every variant of the single-right-hand-side product kernels (row block
+ * size, non-temporal or cached operator loads) on this operator, `reps` launches each on
+ * `stream`, and keeps the fastest for later applies.  Uses the operator's own workspace
+ * (allocated if needed) and writes nothing the caller owns.  Times are milliseconds per
+ * launch; entries past `nvar` are unused.
+ */
+typedef struct {
+    int nvar;
+    int var_n, var_c;    /* chosen variants */
+    double ms_n[8];      /* product for F   */
+    double ms_c[8];      /* product for F^T */
+} btoep_tune_result;
+
+btoep_status btoep_autotune(btoep_op op, int reps, void* stream, btoep_tune_result* out);
+
+/* Pins the variants (0 .. nvar-1) and whether k >= 2 right-hand sides use the matrix-core
+ * kernels (use_mfma != 0, the default) or one single-vector product per right-hand side. */
+btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma);
+
+/*
  * Per-kernel timing for measurement: while enabled, every kernel an apply launches on this
  * operator is bracketed by HIP events recorded on the same stream.  btoep_profile_read waits
  * for the recorded events and returns, per kernel name, the launches and the summed

@@ -55,6 +55,11 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("nvar", ctypes.c_int), ("var_n", ctypes.c_int), ("var_c", ctypes.c_int),
+                ("ms_n", ctypes.c_double * 8), ("ms_c", ctypes.c_double * 8)]
+
+
 def load_library(path=LIB_PATH):
     """Load libbtoep.so (raises OSError when it is missing or unloadable)."""
     global _lib
@@ -77,6 +82,8 @@ def load_library(path=LIB_PATH):
                                  vp], st),
         "btoep_cg_solve": ([vp, vp, i64, dbl, dbl, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp,
                             sz, vp], st),
+        "btoep_autotune": ([vp, ctypes.c_int, vp, ctypes.POINTER(TuneResult)], st),
+        "btoep_set_tuning": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
         "btoep_profile_enable": ([vp, ctypes.c_int], st),
         "btoep_profile_read": ([vp, ctypes.POINTER(KernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], st),
         "btoep_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -309,3 +316,21 @@ def btoep_profile_read(op):
     n = ctypes.c_int()
     _check(load_library().btoep_profile_read(op.handle, buf, 16, ctypes.byref(n)), "btoep_profile_read", op.handle)
     return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(n.value)}
+
+
+def btoep_autotune(op, reps=5, stream=None):
+    """Time the single-vector product variants on this operator and keep the fastest.
+
+    Returns {"var_n", "var_c", "ms_n": [...], "ms_c": [...]} (milliseconds per launch).
+    """
+    r = TuneResult()
+    _check(load_library().btoep_autotune(op.handle, int(reps), _stream(stream), ctypes.byref(r)),
+           "btoep_autotune", op.handle)
+    return {"var_n": r.var_n, "var_c": r.var_c, "ms_n": [round(r.ms_n[i], 4) for i in range(r.nvar)],
+            "ms_c": [round(r.ms_c[i], 4) for i in range(r.nvar)]}
+
+
+def btoep_set_tuning(op, var_n, var_c, use_mfma=True):
+    """Pin the single-vector kernel variants and the multi-vector kernel choice."""
+    _check(load_library().btoep_set_tuning(op.handle, int(var_n), int(var_c), 1 if use_mfma else 0),
+           "btoep_set_tuning", op.handle)

@@ -29,6 +29,7 @@ struct btoep_op_s {
     void* tw64 = nullptr;  // exp(-2 pi i t / L), t < L, complex FP64
     void* tw32 = nullptr;  // same, complex FP32
     bool gemm_enabled = true;  // MFMA kernels for several right-hand sides
+    int var_n = 3, var_c = 3;  // single-vector kernel variants (see sbgemv_variants)
     void* ws = nullptr;    // operator-owned workspace (used when the caller passes none)
     size_t ws_cap = 0;
     std::mutex mu;
@@ -224,7 +225,8 @@ hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part,
     if (use_gemm(op, nb))
         return launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b,
                                st);
-    return launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b, st);
+    return launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b, st,
+                           op->var_n);
 }
 
 hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, int64_t vh_b, hipStream_t st) {
@@ -240,12 +242,13 @@ hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, i
                                                       (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st)
                                     : launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
                                                       (const char*)dh + (size_t)r0 * dh_b * 8, dh_b, n,
-                                                      (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st);
+                                                      (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st,
+                                                      op->var_c);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
-    return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st);
+    return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st, op->var_c);
 }
 
 // One pipeline launch sequence over nb <= kMaxBatch right-hand sides.
@@ -627,6 +630,73 @@ btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_pr
     }
     (void)inner_total;
     return all_conv ? BTOEP_OK : BTOEP_ERR_NOT_CONVERGED;
+}
+
+btoep_status btoep_autotune(btoep_op op, int reps, void* stream, btoep_tune_result* out) {
+    if (!op || reps < 1 || !out) return BTOEP_ERR_INVALID_ARG;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    btoep_status s = get_ws(op, apply_layout(op, BTOEP_APPLY_H, 1).total, ws, ws_bytes);
+    if (s != BTOEP_OK) return s;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    const ApplyWs w = apply_layout(op, BTOEP_APPLY_H, 1);
+    char* base = (char*)ws;
+    const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq, nspan = (int)nspan_of(op);
+    const int64_t vh_b = op->nfreq * op->ldv, part_b = op->nfreq * nspan * op->Nd, dh_b = op->nfreq * op->Nd;
+    // defined inputs for the timing runs
+    BT_HIP(op, hipMemsetAsync(base, 0, w.total, st));
+    hipEvent_t a = nullptr, b = nullptr;
+    BT_HIP(op, hipEventCreate(&a));
+    BT_HIP(op, hipEventCreate(&b));
+    const int nvar = std::min(sbgemv_variants(), 8);
+    memset(out, 0, sizeof(*out));
+    out->nvar = nvar;
+    double best_n = 1e30, best_c = 1e30;
+    hipError_t e = hipSuccess;
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+        for (int v = 0; v < nvar && e == hipSuccess; ++v) {
+            auto launch = [&]() {
+                return dir == 0 ? launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, base + w.vh, op->ldv, vh_b,
+                                                  1, base + w.part, nspan, part_b, st, v)
+                                : launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, base + w.dh, dh_b, 1,
+                                                  base + w.vh, op->ldv, vh_b, st, v);
+            };
+            e = launch();
+            if (e == hipSuccess) e = hipEventRecord(a, st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            const double per = (double)ms / reps;
+            if (dir == 0) {
+                out->ms_n[v] = per;
+                if (per < best_n) best_n = per, out->var_n = v;
+            } else {
+                out->ms_c[v] = per;
+                if (per < best_c) best_c = per, out->var_c = v;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) {
+        set_err(op, "autotune", e);
+        return BTOEP_ERR_HIP;
+    }
+    op->var_n = out->var_n;
+    op->var_c = out->var_c;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma) {
+    if (!op || var_n < 0 || var_c < 0 || var_n >= sbgemv_variants() || var_c >= sbgemv_variants())
+        return BTOEP_ERR_INVALID_ARG;
+    op->var_n = var_n;
+    op->var_c = var_c;
+    op->gemm_enabled = use_mfma != 0;
+    return BTOEP_OK;
 }
 
 btoep_status btoep_profile_enable(btoep_op op, int enable) {

@@ -382,13 +382,14 @@ __global__ __launch_bounds__(kFftThreads) void k_dside(const cx<T>* __restrict__
     const int N = plan.N, P = 1 << logP;
     const int col0 = blockIdx.x << logP;
     const cx<T>* __restrict__ pb = part + (int64_t)blockIdx.y * part_batch;
+    const int64_t fs = (int64_t)(N + 1) * nspan;  // partials of one sensor: [f][span], contiguous
 
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
         cx<T> acc = cx<T>{0, 0};
         if (col0 + c < Nd) {
-            const cx<T>* q = pb + (int64_t)f * nspan * Nd + col0 + c;
-            for (int sp = 0; sp < nspan; ++sp) acc = cadd(acc, q[(int64_t)sp * Nd]);
+            const cx<T>* q = pb + (col0 + c) * fs + (int64_t)f * nspan;
+            for (int sp = 0; sp < nspan; ++sp) acc = cadd(acc, q[sp]);
         }
         sh[(f << logP) + c] = acc;
     }
@@ -439,11 +440,19 @@ size_t fft_lds_bytes(int N, int logP, Real r) {
 
 static inline unsigned nblk(int n, int logP) { return (unsigned)((n + (1 << logP) - 1) >> logP); }
 
+// Narrow batches (the data side: Nd columns) get fewer columns per workgroup so that the
+// launch still spreads over the chip; wide ones keep the largest tile that fits.
+static int pick_log_cols(int N, Real r, int ncols, int nb) {
+    int lp = fft_log_cols(N, r);
+    while (lp > 0 && (int64_t)nblk(ncols, lp) * nb < 512) --lp;
+    return lp;
+}
+
 hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_row, int nb, void* out,
                           int64_t out_row, int64_t out_batch, int Nt, int ncols, const FftPlan& plan,
                           const void* tw, hipStream_t st) {
-    const int lp = fft_log_cols(plan.N, r);
-    if (lp < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    const int lp = pick_log_cols(plan.N, r, ncols, nb);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
     if (r == Real::F32 && ir == Real::F32 && os == Stor::C64)
@@ -462,8 +471,8 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
 hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int64_t in_batch, int nb, void* out,
                                   int64_t out_row, int64_t out_batch, int Nt, int ncols, const FftPlan& plan,
                                   const void* tw64, hipStream_t st) {
-    const int lp = fft_log_cols(plan.N, Real::F64);
-    if (lp < 0 || nb <= 0) return hipErrorInvalidValue;
+    if (fft_log_cols(plan.N, Real::F64) < 0 || nb <= 0) return hipErrorInvalidValue;
+    const int lp = pick_log_cols(plan.N, Real::F64, ncols, nb);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, Real::F64);
     const cx<double>* tw = (const cx<double>*)tw64;
@@ -487,8 +496,8 @@ hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int
 hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_batch, int nb, const PtrBatch& out,
                           int64_t out_row, const PtrBatch& add, double add_scale, int Nt, int ncols,
                           const FftPlan& plan, const void* tw, double out_scale, hipStream_t st) {
-    const int lp = fft_log_cols(plan.N, r);
-    if (lp < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    const int lp = pick_log_cols(plan.N, r, ncols, nb);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
     if (r == Real::F32)
@@ -505,9 +514,9 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
 hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch, int nb, const PtrBatch* dout,
                         void* dh, int64_t dh_batch, int Nt, int Nd, const FftPlan& plan, const void* tw,
                         double scale, hipStream_t st) {
-    const int lp = fft_log_cols(plan.N, r);
-    if (lp < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
-    dim3 grid(nblk(Nd, lp), nb), block(kFftThreads);
+    if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
+    const int lp = 0;  // one sensor per workgroup: its partial sums are one contiguous run
+    dim3 grid(Nd, nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
     PtrBatch none{};
     const PtrBatch& d = dout ? *dout : none;

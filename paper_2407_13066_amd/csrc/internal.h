@@ -50,7 +50,7 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
                           const PtrBatch& out, int64_t out_row, const PtrBatch& add, double add_scale,
                           int Nt, int ncols, const FftPlan& plan, const void* tw, double out_scale,
                           hipStream_t st);
-// Data side of F and H: sums split partial sums part[b][f][span][s] over spans, inverse
+// Data side of F and H: sums split partial sums part[b][s][f][span] over spans, inverse
 // transforms along f, keeps j < Nt and scales by `scale`.  With `dout` given, writes the data
 // vector d[b][j][s]; otherwise (H) zero-pads and forward transforms again into dh[b][f][s].
 hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch, int nb,
@@ -61,13 +61,16 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
 // Per-frequency products with the stored operator Fh[f][s][p] (row stride ldF, frequency
 // stride Nd*ldF).  N: part[b][f][span][s] = sum_{p in span} Fh[f][s][p] mh[b][f][p].
 // C: mo[b][f][p] = sum_s conj(Fh[f][s][p]) dh[b][f][s].
+// Partial sums are laid out part[b][s][f][span] (part_batch = Nd * nfreq * nspan).
+// `var` selects a tuning variant (0 .. sbgemv_variants()-1).
 int sbgemv_n_span(Stor st, int64_t Nm);
+int sbgemv_variants();
 hipError_t launch_sbgemv_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
-                           int nspan, int64_t part_batch, hipStream_t s);
+                           int nspan, int64_t part_batch, hipStream_t s, int var);
 hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* dh, int64_t dh_batch, int nb, void* mo, int64_t ldv,
-                           int64_t mo_batch, hipStream_t s);
+                           int64_t mo_batch, hipStream_t s, int var);
 
 // ---- launchers (sbgemm.hip): k >= 2 right-hand sides on the matrix cores ----------------
 // Same operands and outputs as the single-vector launchers above, for nb right-hand sides in

@@ -11,7 +11,7 @@
 // conjugate-transposed pattern [[Re d, Im d], [Im d, -Re d]] (eq. AdjointFFTMatvec).
 //
 //   N (for F):  C_f (Nd x 2k) += Fh_f (Nd x 2Nm) B_f (2Nm x 2k), split over column spans
-//               (partial sums part[r][f][span][s], summed in order by the data-side kernel).
+//               (partial sums part[r][s][f][span], summed in order by the data-side kernel).
 //               A workgroup keeps the whole Nd x 2k accumulator of its span in registers
 //               and streams the right-hand sides through LDS in chunks of 64 columns.
 //   C (for F^T): O_f^T (2k x Nm) = D_f^T (2k x 2Nd) Fh_f (2Nd x Nm): the operator is the
@@ -73,7 +73,7 @@ template <bool BF, int NT, int kChunk = Chunk<NT>::value>
 __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
                                                            int64_t mh_batch, int nb, cx<float>* __restrict__ part,
-                                                           int CS, int nspan, int64_t part_batch) {
+                                                           int CS, int nspan, int nfreq, int64_t part_batch) {
     constexpr int LDR = kChunk + 2;  // row stride (entries) of a staged chunk
     // entry = float complex (FP32 path) or (hi, lo) packed bf16 pairs (BF16 path): 8 bytes
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
                     const int s = rt0 + 16 * a + 4 * lg + v;
                     if (s < Nd) {
                         float* o = reinterpret_cast<float*>(part + (int64_t)r * part_batch +
-                                                            ((int64_t)f * nspan + span) * Nd + s);
+                                                            ((int64_t)s * nfreq + f) * nspan + span);
                         o[li & 1] = acc[a][n][v];
                     }
                 }
@@ -371,7 +371,8 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     const cx<float>* m = (const cx<float>*)mh;
     cx<float>* p = (cx<float>*)part;
 #define BT_GN(BFV, NTV) \
-    k_sbgemm_n<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, part_batch)
+    k_sbgemm_n<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, \
+                                                  part_batch)
     const bool bf = st == Stor::BF16;
     switch (NT) {
         case 1: if (bf) BT_GN(true, 1); else BT_GN(false, 1); break;

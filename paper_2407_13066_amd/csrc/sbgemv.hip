@@ -53,25 +53,37 @@ struct StorT<bf16c> {
     }
 };
 
-// 32 bytes of the operator (VEC complex entries), two non-temporal 16-byte loads.
-__device__ __forceinline__ void load32_nt(const void* p, u32x4* w) {
+// 32 bytes of the operator (VEC complex entries) as two 16-byte loads; non-temporal when NTL.
+template <bool NTL>
+__device__ __forceinline__ void load32(const void* p, u32x4* w) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
-    w[0] = __builtin_nontemporal_load(q);
-    w[1] = __builtin_nontemporal_load(q + 1);
+    if (NTL) {
+        w[0] = __builtin_nontemporal_load(q);
+        w[1] = __builtin_nontemporal_load(q + 1);
+    } else {
+        w[0] = q[0];
+        w[1] = q[1];
+    }
 }
 
 constexpr int kGemvThreads = 256;
 constexpr int kGemvWaves = kGemvThreads / kWave;
 
 // ---- N direction ----------------------------------------------------------------------
-template <typename S, int RB>
+// Wave w owns row blocks s0 = RB (w + 4 j); for each it walks the span in tiles of 64 lanes x
+// VEC columns.  The (row block, tile) iterations are flattened and software-pipelined: the
+// loads of iteration i+1 are in flight while iteration i is consumed, so the wave never
+// waits for an empty memory pipe (also not across the cross-lane reduction that ends a row
+// block).  Partial sums go to part[b][s][f][span].
+template <typename S, int RB, bool NTL>
 __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__ Fh, int64_t ldF, int Nd, int Nm,
                                                            const cx<typename StorT<S>::A>* __restrict__ mh,
                                                            int64_t ldv, int64_t mh_batch,
                                                            cx<typename StorT<S>::A>* __restrict__ part,
-                                                           int CS, int nspan, int64_t part_batch) {
+                                                           int CS, int nspan, int nfreq, int64_t part_batch) {
     typedef typename StorT<S>::A A;
     constexpr int VEC = StorT<S>::VEC;
+    constexpr int TILE = kWave * VEC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<A>* msh = reinterpret_cast<cx<A>*>(smem_raw);
 
@@ -83,45 +95,72 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__
     __syncthreads();
 
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int ntile = (ncol + TILE - 1) / TILE;
+    const int first = wave * RB;
+    const int nrb = (first < Nd) ? (Nd - first + kGemvWaves * RB - 1) / (kGemvWaves * RB) : 0;
+    const int total = nrb * ntile;
+    if (total == 0) return;
+    // last VEC-aligned column group that lies inside the padded row (loads are clamped to it;
+    // the staged vector is zero past ncol, so clamped lanes add nothing)
+    const int last_col = ((ncol + VEC - 1) / VEC) * VEC - VEC;
     const S* __restrict__ Ff = Fh + (int64_t)f * Nd * ldF + col0;
-    cx<A>* __restrict__ pout = part + (int64_t)b * part_batch + ((int64_t)f * nspan + span) * Nd;
+    cx<A>* __restrict__ pout = part + (int64_t)b * part_batch + (int64_t)f * nspan + span;
+    const int64_t pstride = (int64_t)nfreq * nspan;
 
-    for (int s0 = wave * RB; s0 < Nd; s0 += kGemvWaves * RB) {
-        cx<A> acc[RB];
+    u32x4 wa[RB][2], wb[RB][2];
+    int ij = 0, it = 0;  // issue pointer (row block, tile)
+    auto issue = [&](u32x4(&w)[RB][2]) {
+        const int s0 = first + ij * kGemvWaves * RB;
+        const int col = min((it * kWave + lane) * VEC, last_col);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r] = cx<A>{0, 0};
-#pragma unroll 2
-        for (int t = lane * VEC; t < ncol; t += kWave * VEC) {
-            u32x4 w[RB][2];
+        for (int r = 0; r < RB; ++r) load32<NTL>(Ff + (int64_t)min(s0 + r, Nd - 1) * ldF + col, w[r]);
+        if (++it == ntile) {
+            it = 0;
+            ++ij;
+        }
+    };
+    cx<A> acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = cx<A>{0, 0};
+    int cj = 0, ct = 0;  // consume pointer
+    auto consume = [&](const u32x4(&w)[RB][2]) {
+        const int col = (ct * kWave + lane) * VEC;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const cx<A> mv = msh[col + v];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) cfma(acc[r], StorT<S>::get(w[r], v), mv);
+        }
+        if (++ct == ntile) {
+            const int s0 = first + cj * kGemvWaves * RB;
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                const int s = min(s0 + r, Nd - 1);  // rows past Nd repeat the last one; discarded below
-                load32_nt(Ff + (int64_t)s * ldF + t, w[r]);
+                const A re = wave_sum(acc[r].re), im = wave_sum(acc[r].im);
+                if (lane == 0 && s0 + r < Nd) pout[(int64_t)(s0 + r) * pstride] = cx<A>{re, im};
+                acc[r] = cx<A>{0, 0};
             }
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                const cx<A> mv = msh[t + v];
-#pragma unroll
-                for (int r = 0; r < RB; ++r) cfma(acc[r], StorT<S>::get(w[r], v), mv);
-            }
+            ct = 0;
+            ++cj;
         }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            acc[r].re = wave_sum(acc[r].re);
-            acc[r].im = wave_sum(acc[r].im);
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-                if (s0 + r < Nd) pout[s0 + r] = acc[r];
+    };
+    issue(wa);
+    for (int i = 0; i < total; i += 2) {
+        if (i + 1 < total) issue(wb);
+        consume(wa);
+        if (i + 1 < total) {
+            if (i + 2 < total) issue(wa);
+            consume(wb);
         }
     }
 }
 
 // ---- C direction ----------------------------------------------------------------------
+// Lanes own VEC consecutive columns; rows are consumed RB at a time with the next RB rows'
+// loads already in flight.  dh_f is staged in LDS zero-padded to a multiple of 2 RB rows
+// (rows past Nd load row Nd-1 and are multiplied by zero).
 constexpr int kDChunk = 1024;
 
-template <typename S, int RB>
+template <typename S, int RB, bool NTL>
 __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__ Fh, int64_t ldF, int Nd, int Nm,
                                                            const cx<typename StorT<S>::A>* __restrict__ dh,
                                                            int64_t dh_batch,
@@ -133,7 +172,8 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
     const int f = blockIdx.y, b = blockIdx.z;
     const int col = (blockIdx.x * kGemvThreads + threadIdx.x) * VEC;
     const bool active = col < Nm;
-    const S* __restrict__ Ff = Fh + (int64_t)f * Nd * ldF + col;
+    const int colc = min(col, ((Nm + VEC - 1) / VEC) * VEC - VEC);
+    const S* __restrict__ Ff = Fh + (int64_t)f * Nd * ldF + colc;
     const cx<A>* __restrict__ dv = dh + (int64_t)b * dh_batch + (int64_t)f * Nd;
     cx<A> acc[VEC];
 #pragma unroll
@@ -141,29 +181,29 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
 
     for (int c0 = 0; c0 < Nd; c0 += kDChunk) {
         const int ns = min(kDChunk, Nd - c0);
+        const int nsp = (ns + 2 * RB - 1) / (2 * RB) * (2 * RB);  // <= kDChunk: kDChunk is a multiple of 2 RB
         __syncthreads();
-        for (int i = threadIdx.x; i < ns; i += kGemvThreads) dsh[i] = dv[c0 + i];
+        for (int i = threadIdx.x; i < nsp; i += kGemvThreads) dsh[i] = (i < ns) ? dv[c0 + i] : cx<A>{0, 0};
         __syncthreads();
-        if (active) {
-            int s = 0;
-            for (; s + RB <= ns; s += RB) {
-                u32x4 w[RB][2];
+        u32x4 wa[RB][2], wb[RB][2];
+        auto issue = [&](int s, u32x4(&w)[RB][2]) {
 #pragma unroll
-                for (int r = 0; r < RB; ++r) load32_nt(Ff + (int64_t)(c0 + s + r) * ldF, w[r]);
+            for (int r = 0; r < RB; ++r) load32<NTL>(Ff + (int64_t)min(c0 + s + r, Nd - 1) * ldF, w[r]);
+        };
+        auto consume = [&](int s, const u32x4(&w)[RB][2]) {
 #pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    const cx<A> d = dsh[s + r];
+            for (int r = 0; r < RB; ++r) {
+                const cx<A> d = dsh[s + r];
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) cfmac(acc[v], StorT<S>::get(w[r], v), d);
-                }
+                for (int v = 0; v < VEC; ++v) cfmac(acc[v], StorT<S>::get(w[r], v), d);
             }
-            for (; s < ns; ++s) {
-                u32x4 w[2];
-                load32_nt(Ff + (int64_t)(c0 + s) * ldF, w);
-                const cx<A> d = dsh[s];
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) cfmac(acc[v], StorT<S>::get(w, v), d);
-            }
+        };
+        issue(0, wa);
+        for (int s = 0; s < nsp; s += 2 * RB) {
+            issue(s + RB, wb);
+            consume(s, wa);
+            if (s + 2 * RB < nsp) issue(s + 2 * RB, wa);
+            consume(s + RB, wb);
         }
     }
     if (active) {
@@ -185,54 +225,81 @@ int sbgemv_n_span(Stor st, int64_t Nm) {
     return (int)(cs < need ? cs : need);
 }
 
-hipError_t launch_sbgemv_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
-                           int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
-                           hipStream_t s) {
-    const int CS = sbgemv_n_span(st, Nm);
-    if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
-    dim3 grid(nspan, nfreq, nb), block(kGemvThreads);
-    constexpr int RB = 4;
-    switch (st) {
-        case Stor::C128:
-            k_sbgemv_n<cx<double>, RB><<<grid, block, CS * sizeof(cx<double>), s>>>(
-                (const cx<double>*)Fh, ldF, Nd, Nm, (const cx<double>*)mh, ldv, mh_batch, (cx<double>*)part, CS,
-                nspan, part_batch);
-            break;
-        case Stor::C64:
-            k_sbgemv_n<cx<float>, RB><<<grid, block, CS * sizeof(cx<float>), s>>>(
-                (const cx<float>*)Fh, ldF, Nd, Nm, (const cx<float>*)mh, ldv, mh_batch, (cx<float>*)part, CS,
-                nspan, part_batch);
-            break;
-        case Stor::BF16:
-            k_sbgemv_n<bf16c, RB><<<grid, block, CS * sizeof(cx<float>), s>>>(
-                (const bf16c*)Fh, ldF, Nd, Nm, (const cx<float>*)mh, ldv, mh_batch, (cx<float>*)part, CS, nspan,
-                part_batch);
-            break;
+// Variant ids: bit 0 = non-temporal operator loads; bits 1.. = row-block index (N: RB 2/4/8,
+// C: RB 4/8/16).  The default is what the autotuner measured best on MI355X.
+int sbgemv_variants() { return 6; }
+
+template <typename S, typename A>
+static hipError_t run_n(int var, dim3 grid, size_t lds, hipStream_t s, const void* Fh, int64_t ldF, int Nd, int Nm,
+                        const void* mh, int64_t ldv, int64_t mh_batch, void* part, int CS, int nspan, int nfreq,
+                        int64_t part_batch) {
+#define BT_N(RBV, NTV)                                                                                         \
+    k_sbgemv_n<S, RBV, NTV><<<grid, kGemvThreads, lds, s>>>((const S*)Fh, ldF, Nd, Nm, (const cx<A>*)mh, ldv, \
+                                                            mh_batch, (cx<A>*)part, CS, nspan, nfreq, part_batch)
+    switch (var) {
+        case 0: BT_N(2, false); break;
+        case 1: BT_N(2, true); break;
+        case 2: BT_N(4, false); break;
+        case 3: BT_N(4, true); break;
+        case 4: BT_N(8, false); break;
+        default: BT_N(8, true); break;
     }
+#undef BT_N
     return hipGetLastError();
 }
 
-hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* dh,
-                           int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s) {
-    const int per = kGemvThreads * stor_vec(st);
-    dim3 grid((unsigned)((Nm + per - 1) / per), nfreq, nb), block(kGemvThreads);
-    constexpr int RB = 8;
+template <typename S, typename A>
+static hipError_t run_c(int var, dim3 grid, hipStream_t s, const void* Fh, int64_t ldF, int Nd, int Nm, const void* dh,
+                        int64_t dh_batch, void* mo, int64_t ldv, int64_t mo_batch) {
+#define BT_C(RBV, NTV)                                                                                          \
+    k_sbgemv_c<S, RBV, NTV><<<grid, kGemvThreads, 0, s>>>((const S*)Fh, ldF, Nd, Nm, (const cx<A>*)dh, dh_batch, \
+                                                          (cx<A>*)mo, ldv, mo_batch)
+    switch (var) {
+        case 0: BT_C(4, false); break;
+        case 1: BT_C(4, true); break;
+        case 2: BT_C(8, false); break;
+        case 3: BT_C(8, true); break;
+        case 4: BT_C(16, false); break;
+        default: BT_C(16, true); break;
+    }
+#undef BT_C
+    return hipGetLastError();
+}
+
+hipError_t launch_sbgemv_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
+                           int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
+                           hipStream_t s, int var) {
+    const int CS = sbgemv_n_span(st, Nm);
+    if (nspan != (Nm + CS - 1) / CS || var < 0 || var >= sbgemv_variants()) return hipErrorInvalidValue;
+    dim3 grid(nspan, nfreq, nb);
     switch (st) {
         case Stor::C128:
-            k_sbgemv_c<cx<double>, RB><<<grid, block, 0, s>>>((const cx<double>*)Fh, ldF, Nd, Nm,
-                                                              (const cx<double>*)dh, dh_batch, (cx<double>*)mo,
-                                                              ldv, mo_batch);
-            break;
+            return run_n<cx<double>, double>(var, grid, CS * sizeof(cx<double>), s, Fh, ldF, Nd, Nm, mh, ldv,
+                                             mh_batch, part, CS, nspan, nfreq, part_batch);
         case Stor::C64:
-            k_sbgemv_c<cx<float>, RB><<<grid, block, 0, s>>>((const cx<float>*)Fh, ldF, Nd, Nm, (const cx<float>*)dh,
-                                                             dh_batch, (cx<float>*)mo, ldv, mo_batch);
-            break;
+            return run_n<cx<float>, float>(var, grid, CS * sizeof(cx<float>), s, Fh, ldF, Nd, Nm, mh, ldv, mh_batch,
+                                           part, CS, nspan, nfreq, part_batch);
         case Stor::BF16:
-            k_sbgemv_c<bf16c, RB><<<grid, block, 0, s>>>((const bf16c*)Fh, ldF, Nd, Nm, (const cx<float>*)dh,
-                                                         dh_batch, (cx<float>*)mo, ldv, mo_batch);
-            break;
+            return run_n<bf16c, float>(var, grid, CS * sizeof(cx<float>), s, Fh, ldF, Nd, Nm, mh, ldv, mh_batch,
+                                       part, CS, nspan, nfreq, part_batch);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* dh,
+                           int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s, int var) {
+    if (var < 0 || var >= sbgemv_variants()) return hipErrorInvalidValue;
+    const int per = kGemvThreads * stor_vec(st);
+    dim3 grid((unsigned)((Nm + per - 1) / per), nfreq, nb);
+    switch (st) {
+        case Stor::C128:
+            return run_c<cx<double>, double>(var, grid, s, Fh, ldF, Nd, Nm, dh, dh_batch, mo, ldv, mo_batch);
+        case Stor::C64:
+            return run_c<cx<float>, float>(var, grid, s, Fh, ldF, Nd, Nm, dh, dh_batch, mo, ldv, mo_batch);
+        case Stor::BF16:
+            return run_c<bf16c, float>(var, grid, s, Fh, ldF, Nd, Nm, dh, dh_batch, mo, ldv, mo_batch);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace btoep

@@ -202,3 +202,29 @@ def test_query_and_workspace(bt):
 def test_unsupported_length_is_an_error(bt):
     with pytest.raises(bt.BtoepError):
         bt.btoep_create(np.zeros((5000, 1, 1)), "f64")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_every_kernel_variant_and_autotune(bt, storage):
+    """Each tuning variant of the single-vector products, and the per-vector path for several
+    right-hand sides, matches the oracle; autotune returns a valid choice."""
+    rng = np.random.default_rng(51)
+    Nt, Nd, Nm = 23, 19, 4099 + 512
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / 4.0)[:, None, None]
+    op = make(bt, blocks, storage)
+    m = rng.standard_normal((2, Nt, Nm))
+    d = rng.standard_normal((2, Nt, Nd))
+    vt = op.vector_dtype
+    Fm_ref, FTd_ref = oracle.apply_F(blocks, m), oracle.apply_FT(blocks, d)
+    for var in range(6):
+        for mfma in (True, False):
+            bt.btoep_set_tuning(op, var, var, mfma)
+            Fm = bt.btoep_apply_F(op, to_dev(m, vt)).double().cpu().numpy()
+            FTd = bt.btoep_apply_FT(op, to_dev(d, vt)).double().cpu().numpy()
+            for r in range(2):
+                assert oracle.rel_l2(Fm[r], Fm_ref[r]) <= TOL[storage], (var, mfma)
+                assert oracle.rel_l2(FTd[r], FTd_ref[r]) <= TOL[storage], (var, mfma)
+    t = bt.btoep_autotune(op, reps=2)
+    assert 0 <= t["var_n"] < 6 and 0 <= t["var_c"] < 6 and len(t["ms_n"]) == 6
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_set_tuning(op, 6, 0)
