@@ -56,6 +56,89 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
+def serving_benchmark(bt, n_req, rates, seed=13066):
+    """Continuous-batching server over the three resident serving operators (FP32 storage):
+    a burst measures capacity, then Poisson arrivals at fractions of it give p50 / p99
+    latency and right-hand-side applies per second.  Request mix: kind uniform over
+    F / FT / H / CG, operator uniform, k uniform in 1..16; H and CG use noise_prec = 1e4,
+    prior_prec = 1e-3; CG stops at relative residual 1e-6 (at most 500 iterations)."""
+    import torch
+    import synth
+    from paper_2407_13066_amd.serving import GpuExecutor, Request, Server, percentile
+
+    shapes = synth.WORKLOADS["serving-3ops"]["ops"]
+    ops = {}
+    for i, (Nt, Nd, Nm) in enumerate(shapes):
+        blocks = synth.blocks(Nt, Nd, Nm, Nt / 7.0, stream=10 + i)
+        ops["ABC"[i]] = bt.btoep_create(blocks, "f32")
+        del blocks
+    log("serving operators: " + ", ".join("%s %s %.2f GB" % (n, shapes[i], ops[n].info["fhat_bytes"] / 1e9)
+                                          for i, n in enumerate("ABC")))
+    for op in ops.values():
+        bt.btoep_autotune(op, reps=2)
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    kinds = ("F", "FT", "H", "CG")
+
+    def make(rid):
+        name = "ABC"[int(rng.integers(3))]
+        op = ops[name]
+        kind = kinds[int(rng.integers(4))]
+        k = int(rng.integers(1, 17))
+        x = torch.randn((k, op.Nt, op.Nd if kind == "FT" else op.Nm), generator=gen, device="cuda")
+        return Request(rid=rid, op=name, kind=kind, x=x, noise_prec=1e4, prior_prec=1e-3, rtol=1e-6, max_iter=500)
+
+    def run(arrivals):
+        ex = GpuExecutor(ops, n_streams=2, max_batch=32)
+        srv = Server(ex, hbm_budget=48 << 30, max_batch=32, n_streams=2, poll_every=4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = srv.run(arrivals, t0=t0, timeout=600)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = [r.latency * 1e3 for r in done]
+        rhs = sum(srv.rhs_applies.values())
+        return srv, done, {"requests": len(done), "wall_s": round(wall, 3),
+                           "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+                           "requests_per_s": round(len(done) / wall, 2), "rhs_applies_per_s": round(rhs / wall, 1),
+                           "rhs_applies_by_pipeline": dict(srv.rhs_applies), "launches": srv.launches,
+                           "cg_iters_mean": round(float(np.mean([r.iters for r in done if r.kind == "CG"] or [0])), 1),
+                           "cg_unconverged": sum(1 for r in done if r.kind == "CG" and not r.converged),
+                           "peak_request_GB": round(srv.peak_used / 1e9, 2)}
+
+    burst = [(0.0, make(i)) for i in range(min(n_req, 60))]
+    _, _, cap = run(burst)
+    capacity = cap["requests_per_s"]
+    log("serving capacity (burst of %d): %.1f requests/s" % (len(burst), capacity))
+    out = {"operators": {n: list(shapes[i]) for i, n in enumerate("ABC")}, "storage": "c64",
+           "capacity_requests_per_s": capacity, "burst": cap, "rates": {}}
+    last = None
+    for frac in rates:
+        lam = frac * capacity
+        t, arrivals = 0.0, []
+        for i in range(n_req):
+            t += float(rng.exponential(1.0 / lam))
+            arrivals.append((t, make(1000 * (1 + len(out["rates"])) + i)))
+        srv, done, res = run(arrivals)
+        out["rates"]["%.2fx" % frac] = res
+        log("serving at %.2fx capacity: p50 %.2f ms, p99 %.2f ms, %.0f RHS-applies/s" % (
+            frac, res["p50_ms"], res["p99_ms"], res["rhs_applies_per_s"]))
+        last = done
+    # the same request alone: a few requests of the last run, rerun one by one
+    worst = 0.0
+    for req in [r for r in last if r.kind != "CG"][:6]:
+        op = ops[req.op]
+        ref = {"F": lambda: bt.btoep_apply_F(op, req.x), "FT": lambda: bt.btoep_apply_FT(op, req.x),
+               "H": lambda: bt.btoep_apply_H(op, req.x, req.noise_prec, req.prior_prec)}[req.kind]()
+        torch.cuda.synchronize()
+        a, b = req.out.double(), ref.double()
+        worst = max(worst, float(torch.linalg.norm(a - b) / torch.linalg.norm(b)))
+    out["mixed_vs_alone_max_rel_diff"] = worst
+    for op in ops.values():
+        op.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=150,
+                    help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
                     help="parameter columns of the operator the CPU oracle is timed on")
     args = ap.parse_args()
@@ -216,6 +301,12 @@ def main():
                                                 ns, Nm, runs, t / runs,
                                                 "" if ns == Nm else ", scaled x%.0f (cost is linear in Nm)" % (Nm / ns))}
         log("cpu oracle %.2f s per H" % per)
+
+    if args.serving_requests > 0:
+        op.destroy()
+        del blocks
+        torch.cuda.empty_cache()
+        result["serving"] = serving_benchmark(bt, args.serving_requests, rates=(0.5, 0.9))
 
     print(json.dumps(result), flush=True)
     return 0

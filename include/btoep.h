@@ -201,6 +201,33 @@ typedef struct {
 btoep_status btoep_profile_enable(btoep_op op, int enable);
 btoep_status btoep_profile_read(btoep_op op, btoep_kernel_time* out, int max, int* count);
 
+/*
+ * Stepwise CG, for servers that batch the H applications of many solves with other work
+ * (paper section 2.2).  The caller applies H itself (btoep_apply_H / btoep_apply_batched on
+ * the vectors returned by btoep_cg_vectors) and then calls btoep_cg_update; everything else
+ * (inner products in FP64, scalar recurrences, vector updates) runs on the device.
+ *   btoep_cg_start : state for k right-hand sides; x (op vector type, [k][Nt][Nm], caller
+ *                    owned) is set to 0, r = p = b; stops a right-hand side once
+ *                    ||r|| <= rtol ||b|| (recurrence residual).  Allocates its vectors.
+ *   btoep_cg_vectors : device pointers of the stacked p and Ap arrays ([k][Nt][Nm] each).
+ *   btoep_cg_update  : after Ap = H p: x += alpha p, r -= alpha Ap, p = r + beta p.
+ *   btoep_cg_poll    : enqueue a copy of the scalars to pinned host memory on `stream`.
+ *   btoep_cg_status  : non-blocking; ready = 1 once the last poll landed, then active =
+ *                      right-hand sides still iterating, iters = largest iteration count,
+ *                      rel_res (host [k], may be NULL) = ||r|| / ||b|| per right-hand side.
+ *   btoep_cg_end     : releases the state (synchronises the device).
+ * All calls on one state must be ordered on one stream.
+ */
+typedef struct btoep_cg_s* btoep_cg;
+
+btoep_status btoep_cg_start(btoep_op op, int64_t k, double noise_prec, double prior_prec, const void* b, void* x,
+                            double rtol, void* stream, btoep_cg* out);
+btoep_status btoep_cg_vectors(btoep_cg cg, void** p, void** Ap);
+btoep_status btoep_cg_update(btoep_cg cg, void* stream);
+btoep_status btoep_cg_poll(btoep_cg cg, void* stream);
+btoep_status btoep_cg_status(btoep_cg cg, int* ready, int* active, int* iters, double* rel_res);
+btoep_status btoep_cg_end(btoep_cg cg);
+
 /* Static text for a status code. */
 const char* btoep_status_string(btoep_status s);
 

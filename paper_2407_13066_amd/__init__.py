@@ -86,6 +86,13 @@ def load_library(path=LIB_PATH):
         "btoep_set_tuning": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
         "btoep_profile_enable": ([vp, ctypes.c_int], st),
         "btoep_profile_read": ([vp, ctypes.POINTER(KernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], st),
+        "btoep_cg_start": ([vp, i64, dbl, dbl, vp, vp, dbl, vp, ctypes.POINTER(vp)], st),
+        "btoep_cg_vectors": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp)], st),
+        "btoep_cg_update": ([vp, vp], st),
+        "btoep_cg_poll": ([vp, vp], st),
+        "btoep_cg_status": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], st),
+        "btoep_cg_end": ([vp], st),
         "btoep_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "btoep_last_error": ([vp], ctypes.c_char_p),
     }
@@ -334,3 +341,76 @@ def btoep_set_tuning(op, var_n, var_c, use_mfma=True):
     """Pin the single-vector kernel variants and the multi-vector kernel choice."""
     _check(load_library().btoep_set_tuning(op.handle, int(var_n), int(var_c), 1 if use_mfma else 0),
            "btoep_set_tuning", op.handle)
+
+
+class CgState:
+    """Stepwise CG on one operator (btoep_cg_*): the caller applies H to ``p`` into ``Ap``."""
+
+    def __init__(self, op, handle, k):
+        self.op, self.handle, self.k = op, handle, k
+        p, ap = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(load_library().btoep_cg_vectors(handle, ctypes.byref(p), ctypes.byref(ap)), "btoep_cg_vectors",
+               op.handle)
+        self.p_ptr, self.ap_ptr = p.value, ap.value
+        self.vec_bytes = op.Nt * op.Nm * (8 if op.storage == "f64" else 4)
+
+    def p(self, r):
+        return self.p_ptr + r * self.vec_bytes
+
+    def ap(self, r):
+        return self.ap_ptr + r * self.vec_bytes
+
+    def end(self):
+        if self.handle:
+            load_library().btoep_cg_end(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.end()
+        except Exception:
+            pass
+
+
+def btoep_cg_start(op, b, x, rtol, noise_prec=1.0, prior_prec=1.0, stream=None):
+    """Start stepwise CG for the stacked right-hand sides b (x receives the solution, zeroed here)."""
+    b3 = _vec(op, b, (op.Nt, op.Nm), "b")
+    x3 = _vec(op, x, (op.Nt, op.Nm), "x")
+    h = ctypes.c_void_p()
+    _check(load_library().btoep_cg_start(op.handle, b3.shape[0], float(noise_prec), float(prior_prec),
+                                         ctypes.c_void_p(b3.data_ptr()), ctypes.c_void_p(x3.data_ptr()),
+                                         float(rtol), _stream(stream), ctypes.byref(h)), "btoep_cg_start", op.handle)
+    return CgState(op, h, b3.shape[0])
+
+
+def btoep_cg_update(cg, stream=None):
+    _check(load_library().btoep_cg_update(cg.handle, _stream(stream)), "btoep_cg_update", cg.op.handle)
+
+
+def btoep_cg_poll(cg, stream=None):
+    _check(load_library().btoep_cg_poll(cg.handle, _stream(stream)), "btoep_cg_poll", cg.op.handle)
+
+
+def btoep_cg_status(cg):
+    """(ready, active, iters, [rel residual per right-hand side]) -- never blocks."""
+    ready, active, iters = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rel = (ctypes.c_double * cg.k)()
+    _check(load_library().btoep_cg_status(cg.handle, ctypes.byref(ready), ctypes.byref(active),
+                                          ctypes.byref(iters), rel), "btoep_cg_status", cg.op.handle)
+    return bool(ready.value), active.value, iters.value, list(rel)
+
+
+def btoep_cg_end(cg):
+    cg.end()
+
+
+def btoep_apply_batched_ptrs(op, which, in_ptrs, out_ptrs, noise_prec=1.0, prior_prec=1.0, ws=None, stream=None):
+    """Pointer-array apply on raw device addresses (ints); see btoep_apply_batched."""
+    k = len(in_ptrs)
+    if k != len(out_ptrs) or k > MAX_BATCH:
+        raise ValueError("need len(in_ptrs) == len(out_ptrs) <= %d" % MAX_BATCH)
+    PA = ctypes.c_void_p * max(k, 1)
+    wp, wn = _ws(ws)
+    _check(load_library().btoep_apply_batched(op.handle, WHICH[which], k, PA(*in_ptrs), PA(*out_ptrs),
+                                              float(noise_prec), float(prior_prec), wp, wn, _stream(stream)),
+           "btoep_apply_batched", op.handle)

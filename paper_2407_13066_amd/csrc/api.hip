@@ -699,6 +699,139 @@ btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma) {
     return BTOEP_OK;
 }
 
+}  // extern "C"
+
+struct btoep_cg_s {
+    btoep_op op = nullptr;
+    int64_t k = 0, n = 0;
+    void* x = nullptr;
+    void* r = nullptr;
+    void* p = nullptr;
+    void* Ap = nullptr;
+    double* sc = nullptr;
+    double* tmp = nullptr;
+    double* host = nullptr;  // pinned copy of the scalars
+    hipEvent_t ev = nullptr;
+    bool polled = false;
+};
+
+extern "C" {
+
+btoep_status btoep_cg_end(btoep_cg cg) {
+    if (!cg) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(cg->op->device);
+    (void)hipDeviceSynchronize();
+    for (void* q : {cg->r, cg->p, cg->Ap, (void*)cg->sc, (void*)cg->tmp})
+        if (q) (void)hipFree(q);
+    if (cg->host) (void)hipHostFree(cg->host);
+    if (cg->ev) (void)hipEventDestroy(cg->ev);
+    delete cg;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_start(btoep_op op, int64_t k, double noise_prec, double prior_prec, const void* b, void* x,
+                            double rtol, void* stream, btoep_cg* out) {
+    (void)noise_prec;
+    (void)prior_prec;
+    if (!op || !out || !b || !x || k < 1 || k > kMaxBatch || !(rtol > 0.0)) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    btoep_cg cg = new (std::nothrow) btoep_cg_s();
+    if (!cg) return BTOEP_ERR_OUT_OF_MEMORY;
+    cg->op = op;
+    cg->k = k;
+    cg->n = op->Nt * op->Nm;
+    cg->x = x;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t vb = (size_t)k * cg->n * vbytes(op);
+    const Real rv = op->vreal;
+    hipError_t e = hipMalloc(&cg->r, vb);
+    if (e == hipSuccess) e = hipMalloc(&cg->p, vb);
+    if (e == hipSuccess) e = hipMalloc(&cg->Ap, vb);
+    if (e == hipSuccess) e = hipMalloc((void**)&cg->sc, (size_t)k * kScal * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&cg->tmp, dot_tmp_doubles((int)k) * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&cg->host, (size_t)k * kScal * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&cg->ev, hipEventDisableTiming);
+    const int nb = (int)k;
+    const int64_t n = cg->n;
+    if (e == hipSuccess) {
+        std::vector<double> zeros((size_t)k * kScal, 0.0);
+        e = hipMemcpyAsync(cg->sc, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e == hipSuccess) e = launch_axpbz(rv, x, 0.0, rv, b, 0.0, rv, nullptr, n, nb, n, st);      // x = 0
+    if (e == hipSuccess) e = launch_axpbz(rv, cg->r, 1.0, rv, b, 0.0, rv, nullptr, n, nb, n, st);  // r = b
+    if (e == hipSuccess) e = launch_axpbz(rv, cg->p, 1.0, rv, b, 0.0, rv, nullptr, n, nb, n, st);  // p = b
+    for (int slot : {kScRR, kScBB, kScRH})
+        if (e == hipSuccess) e = launch_dot(rv, b, b, n, nb, n, cg->sc, slot, 0, cg->tmp, st);
+    // stop on ||r||^2 <= rtol^2 ||b||^2; outer test 0 keeps every nonzero right-hand side active
+    if (e == hipSuccess) e = launch_cg_init_scalars(cg->sc, nb, rtol * rtol, 0.0, st);
+    if (e != hipSuccess) {
+        set_err(op, "cg_start", e);
+        btoep_cg_end(cg);
+        return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+    }
+    *out = cg;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_vectors(btoep_cg cg, void** p, void** Ap) {
+    if (!cg || !p || !Ap) return BTOEP_ERR_INVALID_ARG;
+    *p = cg->p;
+    *Ap = cg->Ap;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_update(btoep_cg cg, void* stream) {
+    if (!cg) return BTOEP_ERR_INVALID_ARG;
+    btoep_op op = cg->op;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    const Real rv = op->vreal;
+    const int nb = (int)cg->k;
+    const int64_t n = cg->n;
+    BT_HIP(op, launch_dot(rv, cg->p, cg->Ap, n, nb, n, cg->sc, kScPAP, kScPAP, cg->tmp, st));
+    BT_HIP(op, launch_cg_xr(rv, rv, cg->x, cg->r, cg->p, cg->Ap, n, nb, n, cg->sc, st));
+    BT_HIP(op, launch_dot(rv, cg->r, cg->r, n, nb, n, cg->sc, kScRRN, kScRRN, cg->tmp, st));
+    BT_HIP(op, launch_cg_p(rv, cg->p, cg->r, n, nb, n, cg->sc, st));
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_poll(btoep_cg cg, void* stream) {
+    if (!cg) return BTOEP_ERR_INVALID_ARG;
+    btoep_op op = cg->op;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    BT_HIP(op, hipMemcpyAsync(cg->host, cg->sc, (size_t)cg->k * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
+    BT_HIP(op, hipEventRecord(cg->ev, st));
+    cg->polled = true;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_status(btoep_cg cg, int* ready, int* active, int* iters, double* rel_res) {
+    if (!cg || !ready) return BTOEP_ERR_INVALID_ARG;
+    *ready = 0;
+    if (!cg->polled) return BTOEP_OK;
+    DeviceGuard g(cg->op->device);
+    const hipError_t q = hipEventQuery(cg->ev);
+    if (q == hipErrorNotReady) return BTOEP_OK;
+    if (q != hipSuccess) {
+        set_err(cg->op, "cg_status", q);
+        return BTOEP_ERR_HIP;
+    }
+    *ready = 1;
+    int act = 0, it = 0;
+    for (int64_t i = 0; i < cg->k; ++i) {
+        const double* h = cg->host + i * kScal;
+        act += h[kScACT] != 0.0;
+        it = std::max(it, (int)h[kScIT]);
+        if (rel_res) rel_res[i] = h[kScBB] > 0 ? std::sqrt(h[kScRR] / h[kScBB]) : 0.0;
+    }
+    if (active) *active = act;
+    if (iters) *iters = it;
+    return BTOEP_OK;
+}
+
 btoep_status btoep_profile_enable(btoep_op op, int enable) {
     if (!op) return BTOEP_ERR_INVALID_ARG;
     DeviceGuard g(op->device);

@@ -154,9 +154,18 @@ struct Dft<7, DIR, T> : DftOdd<7, DIR, T> {};
 // W_{Ns R}^{k r} (k = j mod Ns) and writes its outputs to (j - k) R + k + r Ns.  The
 // twiddle table holds exp(-2 pi i t / (2N)), t < 2N, so W_{Ns R}^{k r} is entry
 // 2 k r N / (Ns R).  Each thread keeps its butterflies in registers across the barrier,
-// which lets the pass run in place.
-template <typename T, int R, int DIR, int CMAX>
-__device__ __forceinline__ void stockham_pass(cx<T>* sh, int N, int logP, int Ns, const cx<T>* __restrict__ tw) {
+// which lets the pass run in place.  The read/compute phase has no branches (threads past
+// the last butterfly redo the last one and do not store), so all of a thread's LDS and
+// twiddle reads can be in flight together.
+// Dynamic LDS of every FFT kernel: data (N+1) x P complex, then (when staged) the twiddles.
+extern __shared__ __align__(16) unsigned char fft_smem[];
+
+// Each pass is its own (non-inlined) function so that register allocation is per radix;
+// it addresses the data through the kernel's dynamic LDS symbol so accesses stay LDS ops.
+template <typename T, int R, int DIR, int CMAX, bool TWL>
+__device__ __noinline__ void stockham_pass(int N, int logP, int Ns, size_t tw_off, const cx<T>* __restrict__ twg) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const cx<T>* tw = TWL ? reinterpret_cast<const cx<T>*>(fft_smem + tw_off) : twg;
     constexpr int MAXB = (CMAX + R - 1) / R;
     const int NR = N / R;
     const int nbf = NR << logP;
@@ -166,22 +175,18 @@ __device__ __forceinline__ void stockham_pass(cx<T>* sh, int N, int logP, int Ns
     cx<T> v[MAXB][R];
 #pragma unroll
     for (int bb = 0; bb < MAXB; ++bb) {
-        const int g = tid + bb * kFftThreads;
-        if (g < nbf) {
-            const int c = g & P1, j = g >> logP;
-            const int k = j % Ns;
+        const int g = min(tid + bb * kFftThreads, nbf - 1);
+        const int c = g & P1, j = g >> logP;
+        const int k = j % Ns;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[bb][r] = sh[((j + r * NR) << logP) + c];
-            if (Ns > 1) {
+        for (int r = 0; r < R; ++r) v[bb][r] = sh[((j + r * NR) << logP) + c];
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cx<T> w = tw[2 * (k * r * stride)];
-                    if (DIR > 0) w.im = -w.im;
-                    v[bb][r] = cmul(v[bb][r], w);
-                }
-            }
-            Dft<R, DIR, T>::run(v[bb]);
+        for (int r = 1; r < R; ++r) {
+            cx<T> w = tw[2 * (k * r * stride)];  // k = 0 (first pass) reads W = 1
+            if (DIR > 0) w.im = -w.im;
+            v[bb][r] = cmul(v[bb][r], w);
         }
+        Dft<R, DIR, T>::run(v[bb]);
     }
     __syncthreads();
 #pragma unroll
@@ -198,33 +203,45 @@ __device__ __forceinline__ void stockham_pass(cx<T>* sh, int N, int logP, int Ns
     __syncthreads();
 }
 
-template <typename T, int DIR, int CMAX>
-__device__ void fft_lds(cx<T>* sh, const FftPlan& plan, int logP, const cx<T>* __restrict__ tw) {
+template <typename T, int DIR, int CMAX, bool TWL>
+__device__ void fft_passes(const FftPlan& plan, int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
     int Ns = 1;
     for (int ip = 0; ip < plan.npass; ++ip) {
         const int R = plan.radix[ip];
         switch (R) {
-            case 2: stockham_pass<T, 2, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
-            case 3: stockham_pass<T, 3, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
-            case 4: stockham_pass<T, 4, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
-            case 5: stockham_pass<T, 5, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
-            case 7: stockham_pass<T, 7, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
-            default: stockham_pass<T, 8, DIR, CMAX>(sh, plan.N, logP, Ns, tw); break;
+            case 2: stockham_pass<T, 2, DIR, CMAX, TWL>(plan.N, logP, Ns, tw_off, twg); break;
+            case 3: stockham_pass<T, 3, DIR, CMAX, TWL>(plan.N, logP, Ns, tw_off, twg); break;
+            case 4: stockham_pass<T, 4, DIR, CMAX, TWL>(plan.N, logP, Ns, tw_off, twg); break;
+            case 5: stockham_pass<T, 5, DIR, CMAX, TWL>(plan.N, logP, Ns, tw_off, twg); break;
+            case 7: stockham_pass<T, 7, DIR, CMAX, TWL>(plan.N, logP, Ns, tw_off, twg); break;
+            default: stockham_pass<T, 8, DIR, CMAX, TWL>(plan.N, logP, Ns, tw_off, twg); break;
         }
         Ns *= R;
     }
+}
+
+// All passes of one transform over the P columns in LDS.
+template <typename T, int DIR, int CMAX>
+__device__ __forceinline__ void fft_lds(const FftPlan& plan, int logP, bool twl, size_t tw_off,
+                                        const cx<T>* __restrict__ twg) {
+    if (twl)
+        fft_passes<T, DIR, CMAX, true>(plan, logP, tw_off, twg);
+    else
+        fft_passes<T, DIR, CMAX, false>(plan, logP, tw_off, twg);
 }
 
 template <typename T>
 struct FftCfg;
 template <>
 struct FftCfg<float> {
-    static constexpr int CMAX = 32;  // complex values per thread held across a pass
+    static constexpr int CMAX = 16;  // complex values per thread held across a pass
 };
 template <>
 struct FftCfg<double> {
-    static constexpr int CMAX = 16;
+    static constexpr int CMAX = 8;
 };
+
+constexpr int kLoadUnroll = 8;  // global loads each thread keeps in flight when staging
 
 // ---- storing a complex value in each output format ----------------------------------
 template <typename T>
@@ -277,28 +294,65 @@ __device__ __forceinline__ void c2r_split(cx<T>* sh, int N, int logP, const cx<T
     }
 }
 
+// Twiddle table e^{-2 pi i t / L}, t < L = 2N: copied into LDS behind the data when `twl`,
+// otherwise read from global memory (it stays in the caches).
+template <typename T>
+__device__ __forceinline__ const cx<T>* stage_twiddles(size_t data_bytes, bool twl, int N,
+                                                       const cx<T>* __restrict__ twg) {
+    if (!twl) return twg;
+    cx<T>* t = reinterpret_cast<cx<T>*>(fft_smem + data_bytes);
+#pragma unroll 4
+    for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) t[i] = twg[i];
+    return t;
+}
+
+// Real input rows j < Nt of P columns (zero rows j in [Nt, 2N)) into the packed LDS layout
+// z[n] = x[2n] + i x[2n+1]; loads are issued kLoadUnroll at a time with clamped addresses.
+template <typename T, typename Tin>
+__device__ __forceinline__ void stage_real_rows(T* shr, const Tin* __restrict__ x, int64_t in_row, int Nt, int N,
+                                                int logP, int col0, int ncols) {
+    const int P1 = (1 << logP) - 1;
+    const int total = Nt << logP;
+    for (int e = (Nt << logP) + threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
+        const int c = e & P1, j = e >> logP;
+        shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (T)0;
+    }
+    for (int e0 = 0; e0 < total; e0 += kLoadUnroll * kFftThreads) {
+        T val[kLoadUnroll];
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int e = min(e0 + u * kFftThreads + (int)threadIdx.x, total - 1);
+            const int c = e & P1, j = e >> logP;
+            val[u] = (T)x[(int64_t)j * in_row + min(col0 + c, ncols - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int e = e0 + u * kFftThreads + (int)threadIdx.x;
+            if (e < total) {
+                const int c = e & P1, j = e >> logP;
+                shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (col0 + c < ncols) ? val[u] : (T)0;
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------------------
 // Forward: x (real, Nt rows) -> X (N+1 complex rows).
 template <typename T, typename Tin, typename So>
-__global__ __launch_bounds__(kFftThreads) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
+__global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
                                                          int64_t out_row, int64_t out_batch, int Nt, int ncols,
-                                                         FftPlan plan, int logP, const cx<T>* __restrict__ tw) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
-    T* shr = reinterpret_cast<T*>(smem_raw);
+                                                         FftPlan plan, int logP, const cx<T>* __restrict__ twg,
+                                                         int twl) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const int N = plan.N, P = 1 << logP;
     const int col0 = blockIdx.x << logP;
+    const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
+    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const Tin* __restrict__ x = static_cast<const Tin*>(in.p[blockIdx.y]);
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
-
-    for (int e = threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
-        const int c = e & (P - 1), j = e >> logP;
-        T val = (T)0;
-        if (j < Nt && col0 + c < ncols) val = (T)x[(int64_t)j * in_row + col0 + c];
-        shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = val;
-    }
+    stage_real_rows<T, Tin>(reinterpret_cast<T*>(fft_smem), x, in_row, Nt, N, logP, col0, ncols);
     __syncthreads();
-    fft_lds<T, -1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    fft_lds<T, -1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
         if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
@@ -307,26 +361,21 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_r2c(PtrBatch in, int64_t in
 
 // Setup form (operator block column, FP64 in, batch over rows s with explicit strides).
 template <typename So>
-__global__ __launch_bounds__(kFftThreads) void k_fft_r2c_strided(const double* __restrict__ in, int64_t in_row,
+__global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c_strided(const double* __restrict__ in, int64_t in_row,
                                                                  int64_t in_batch, So* __restrict__ out,
                                                                  int64_t out_row, int64_t out_batch, int Nt,
                                                                  int ncols, FftPlan plan, int logP,
-                                                                 const cx<double>* __restrict__ tw) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<double>* sh = reinterpret_cast<cx<double>*>(smem_raw);
-    double* shr = reinterpret_cast<double*>(smem_raw);
+                                                                 const cx<double>* __restrict__ twg, int twl) {
+    cx<double>* sh = reinterpret_cast<cx<double>*>(fft_smem);
     const int N = plan.N, P = 1 << logP;
     const int col0 = blockIdx.x << logP;
+    const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<double>);
+    const cx<double>* tw = stage_twiddles<double>(tw_off, twl, N, twg);
     const double* __restrict__ x = in + (int64_t)blockIdx.y * in_batch;
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
-    for (int e = threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
-        const int c = e & (P - 1), j = e >> logP;
-        double val = 0.0;
-        if (j < Nt && col0 + c < ncols) val = x[(int64_t)j * in_row + col0 + c];
-        shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = val;
-    }
+    stage_real_rows<double, double>(reinterpret_cast<double*>(fft_smem), x, in_row, Nt, N, logP, col0, ncols);
     __syncthreads();
-    fft_lds<double, -1, FftCfg<double>::CMAX>(sh, plan, logP, tw);
+    fft_lds<double, -1, FftCfg<double>::CMAX>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
         if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
@@ -335,107 +384,125 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_r2c_strided(const double* _
 
 // Inverse: X (N+1 complex rows) -> x_j for j < Nt, times out_scale, plus add_scale * addend.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_c2r(const cx<T>* __restrict__ in, int64_t in_row,
+__global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(const cx<T>* __restrict__ in, int64_t in_row,
                                                          int64_t in_batch, PtrBatch out, int64_t out_row,
                                                          PtrBatch add, T add_scale, int Nt, int ncols,
-                                                         FftPlan plan, int logP, const cx<T>* __restrict__ tw,
-                                                         T out_scale) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
-    const T* shr = reinterpret_cast<const T*>(smem_raw);
-    const int N = plan.N, P = 1 << logP;
+                                                         FftPlan plan, int logP, const cx<T>* __restrict__ twg,
+                                                         int twl, T out_scale) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const T* shr = reinterpret_cast<const T*>(fft_smem);
+    const int N = plan.N, P = 1 << logP, P1 = P - 1;
     const int col0 = blockIdx.x << logP;
+    const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
+    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const cx<T>* __restrict__ y = in + (int64_t)blockIdx.y * in_batch;
     T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.p[blockIdx.y]));
     const T* __restrict__ a = static_cast<const T*>(add.p[blockIdx.y]);
 
-    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
-        const int c = e & (P - 1), f = e >> logP;
-        cx<T> v = cx<T>{0, 0};
-        if (col0 + c < ncols) v = y[(int64_t)f * in_row + col0 + c];
-        sh[(f << logP) + c] = v;
+    const int total = (N + 1) << logP;
+    for (int e0 = 0; e0 < total; e0 += kLoadUnroll * kFftThreads) {
+        cx<T> val[kLoadUnroll];
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int e = min(e0 + u * kFftThreads + (int)threadIdx.x, total - 1);
+            const int c = e & P1, f = e >> logP;
+            val[u] = y[(int64_t)f * in_row + min(col0 + c, ncols - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int e = e0 + u * kFftThreads + (int)threadIdx.x;
+            if (e < total) sh[e] = (col0 + (e & P1) < ncols) ? val[u] : cx<T>{0, 0};
+        }
     }
     __syncthreads();
     c2r_split<T>(sh, N, logP, tw);
     __syncthreads();
-    fft_lds<T, 1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
-    for (int e = threadIdx.x; e < Nt << logP; e += kFftThreads) {
-        const int c = e & (P - 1), j = e >> logP;
-        if (col0 + c >= ncols) continue;
-        const int64_t o = (int64_t)j * out_row + col0 + c;
-        T v = out_scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
-        if (a) v = fma(add_scale, a[o], v);
-        x[o] = v;
+    fft_lds<T, 1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
+    const int nout = Nt << logP;
+    for (int e0 = 0; e0 < nout; e0 += kLoadUnroll * kFftThreads) {
+        T av[kLoadUnroll];
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int e = min(e0 + u * kFftThreads + (int)threadIdx.x, nout - 1);
+            const int c = e & P1, j = e >> logP;
+            av[u] = a ? a[(int64_t)j * out_row + min(col0 + c, ncols - 1)] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int e = e0 + u * kFftThreads + (int)threadIdx.x;
+            const int c = e & P1, j = e >> logP;
+            if (e < nout && col0 + c < ncols) {
+                const T v = out_scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
+                x[(int64_t)j * out_row + col0 + c] = a ? fma(add_scale, av[u], v) : v;
+            }
+        }
     }
 }
 
 // Data side: reduce split partial sums over spans, inverse transform, keep j < Nt, scale;
-// then either store d (F) or zero-pad, forward transform and store the bins (H).
+// then either store d (F) or zero-pad, forward transform and store the bins (H).  One
+// sensor (column) per workgroup, whose partial sums part[b][s][f][span] are contiguous.
 template <typename T, bool HMODE>
-__global__ __launch_bounds__(kFftThreads) void k_dside(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
+__global__ __launch_bounds__(kFftThreads, 2) void k_dside(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
                                                        PtrBatch dout, cx<T>* __restrict__ dh, int64_t dh_batch,
-                                                       int Nt, int Nd, FftPlan plan, int logP,
-                                                       const cx<T>* __restrict__ tw, T scale) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
-    T* shr = reinterpret_cast<T*>(smem_raw);
-    const int N = plan.N, P = 1 << logP;
-    const int col0 = blockIdx.x << logP;
-    const cx<T>* __restrict__ pb = part + (int64_t)blockIdx.y * part_batch;
-    const int64_t fs = (int64_t)(N + 1) * nspan;  // partials of one sensor: [f][span], contiguous
+                                                       int Nt, int Nd, FftPlan plan, const cx<T>* __restrict__ twg,
+                                                       int twl, T scale) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    T* shr = reinterpret_cast<T*>(fft_smem);
+    constexpr int logP = 0;
+    const int N = plan.N;
+    const int s = blockIdx.x;
+    const size_t tw_off = (size_t)(N + 1) * sizeof(cx<T>);
+    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
+    const cx<T>* __restrict__ pb = part + (int64_t)blockIdx.y * part_batch + (int64_t)s * (N + 1) * nspan;
 
-    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
-        const int c = e & (P - 1), f = e >> logP;
+    for (int f = threadIdx.x; f <= N; f += kFftThreads) {
+        const cx<T>* q = pb + (int64_t)f * nspan;
         cx<T> acc = cx<T>{0, 0};
-        if (col0 + c < Nd) {
-            const cx<T>* q = pb + (col0 + c) * fs + (int64_t)f * nspan;
-            for (int sp = 0; sp < nspan; ++sp) acc = cadd(acc, q[sp]);
-        }
-        sh[(f << logP) + c] = acc;
+#pragma unroll 8
+        for (int sp = 0; sp < nspan; ++sp) acc = cadd(acc, q[sp]);
+        sh[f] = acc;
     }
     __syncthreads();
     c2r_split<T>(sh, N, logP, tw);
     __syncthreads();
-    fft_lds<T, 1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    fft_lds<T, 1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
     if (!HMODE) {
         T* __restrict__ d = static_cast<T*>(const_cast<void*>(dout.p[blockIdx.y]));
-        for (int e = threadIdx.x; e < Nt << logP; e += kFftThreads) {
-            const int c = e & (P - 1), j = e >> logP;
-            if (col0 + c < Nd) d[(int64_t)j * Nd + col0 + c] = scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
-        }
+        for (int j = threadIdx.x; j < Nt; j += kFftThreads) d[(int64_t)j * Nd + s] = scale * shr[j];
         return;
     }
     // keep samples j < Nt (scaled), zero the padding, transform forward again
-    for (int e = threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
-        const int c = e & (P - 1), j = e >> logP;
-        const int idx = 2 * (((j >> 1) << logP) + c) + (j & 1);
-        shr[idx] = (j < Nt) ? scale * shr[idx] : (T)0;
-    }
+    for (int j = threadIdx.x; j < 2 * N; j += kFftThreads) shr[j] = (j < Nt) ? scale * shr[j] : (T)0;
     __syncthreads();
-    fft_lds<T, -1, FftCfg<T>::CMAX>(sh, plan, logP, tw);
+    fft_lds<T, -1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
     cx<T>* __restrict__ o = dh + (int64_t)blockIdx.y * dh_batch;
-    for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
-        const int c = e & (P - 1), f = e >> logP;
-        if (col0 + c < Nd) o[(int64_t)f * Nd + col0 + c] = r2c_bin(sh, N, logP, f, c, tw);
-    }
+    for (int f = threadIdx.x; f <= N; f += kFftThreads) o[(int64_t)f * Nd + s] = r2c_bin(sh, N, logP, f, 0, tw);
 }
 
 // ----------------------------------------------------------------------------------------
 static constexpr size_t kFftLdsBudget = 64 * 1024;
 
+static size_t elem_of(Real r) { return r == Real::F64 ? 16 : 8; }
+static int cmax_of(Real r) { return r == Real::F64 ? FftCfg<double>::CMAX : FftCfg<float>::CMAX; }
+
+// Twiddles live in LDS whenever one column plus the table fits.
+static bool twl_of(int N, Real r) { return (size_t)(N + 1 + 2 * N) * elem_of(r) <= kFftLdsBudget; }
+
 int fft_log_cols(int N, Real r) {
-    const size_t elem = (r == Real::F64) ? 16 : 8;
-    const int cmax = (r == Real::F64) ? FftCfg<double>::CMAX : FftCfg<float>::CMAX;
+    const size_t elem = elem_of(r);
+    const size_t tw = twl_of(N, r) ? (size_t)2 * N * elem : 0;
     for (int lp = 6; lp >= 0; --lp) {
         const size_t P = (size_t)1 << lp;
-        if ((size_t)(N + 1) * P * elem <= kFftLdsBudget && (size_t)N * P <= (size_t)cmax * kFftThreads) return lp;
+        if ((size_t)(N + 1) * P * elem + tw <= kFftLdsBudget && (size_t)N * P <= (size_t)cmax_of(r) * kFftThreads)
+            return lp;
     }
     return -1;
 }
 
 size_t fft_lds_bytes(int N, int logP, Real r) {
-    const size_t elem = (r == Real::F64) ? 16 : 8;
-    return (size_t)(N + 1) * ((size_t)1 << logP) * elem;
+    const size_t elem = elem_of(r);
+    return (size_t)(N + 1) * ((size_t)1 << logP) * elem + (twl_of(N, r) ? (size_t)2 * N * elem : 0);
 }
 
 static inline unsigned nblk(int n, int logP) { return (unsigned)((n + (1 << logP) - 1) >> logP); }
@@ -453,16 +520,17 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
                           const void* tw, hipStream_t st) {
     if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int lp = pick_log_cols(plan.N, r, ncols, nb);
+    const int twl = twl_of(plan.N, r);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
     if (r == Real::F32 && ir == Real::F32 && os == Stor::C64)
         k_fft_r2c<float, float, cx<float>><<<grid, block, lds, st>>>(in, in_row, (cx<float>*)out, out_row,
                                                                      out_batch, Nt, ncols, plan, lp,
-                                                                     (const cx<float>*)tw);
+                                                                     (const cx<float>*)tw, twl);
     else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128)
         k_fft_r2c<double, double, cx<double>><<<grid, block, lds, st>>>(in, in_row, (cx<double>*)out, out_row,
                                                                         out_batch, Nt, ncols, plan, lp,
-                                                                        (const cx<double>*)tw);
+                                                                        (const cx<double>*)tw, twl);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -473,21 +541,22 @@ hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int
                                   const void* tw64, hipStream_t st) {
     if (fft_log_cols(plan.N, Real::F64) < 0 || nb <= 0) return hipErrorInvalidValue;
     const int lp = pick_log_cols(plan.N, Real::F64, ncols, nb);
+    const int twl = twl_of(plan.N, Real::F64);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, Real::F64);
     const cx<double>* tw = (const cx<double>*)tw64;
     switch (os) {
         case Stor::C128:
             k_fft_r2c_strided<cx<double>><<<grid, block, lds, st>>>(in, in_row, in_batch, (cx<double>*)out,
-                                                                     out_row, out_batch, Nt, ncols, plan, lp, tw);
+                                                                     out_row, out_batch, Nt, ncols, plan, lp, tw, twl);
             break;
         case Stor::C64:
             k_fft_r2c_strided<cx<float>><<<grid, block, lds, st>>>(in, in_row, in_batch, (cx<float>*)out, out_row,
-                                                                    out_batch, Nt, ncols, plan, lp, tw);
+                                                                    out_batch, Nt, ncols, plan, lp, tw, twl);
             break;
         case Stor::BF16:
             k_fft_r2c_strided<bf16c><<<grid, block, lds, st>>>(in, in_row, in_batch, (bf16c*)out, out_row,
-                                                                out_batch, Nt, ncols, plan, lp, tw);
+                                                                out_batch, Nt, ncols, plan, lp, tw, twl);
             break;
     }
     return hipGetLastError();
@@ -498,15 +567,16 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
                           const FftPlan& plan, const void* tw, double out_scale, hipStream_t st) {
     if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int lp = pick_log_cols(plan.N, r, ncols, nb);
+    const int twl = twl_of(plan.N, r);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
     if (r == Real::F32)
         k_fft_c2r<float><<<grid, block, lds, st>>>((const cx<float>*)in, in_row, in_batch, out, out_row, add,
-                                                   (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw,
+                                                   (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw, twl,
                                                    (float)out_scale);
     else
         k_fft_c2r<double><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out, out_row, add,
-                                                    add_scale, Nt, ncols, plan, lp, (const cx<double>*)tw,
+                                                    add_scale, Nt, ncols, plan, lp, (const cx<double>*)tw, twl,
                                                     out_scale);
     return hipGetLastError();
 }
@@ -515,29 +585,29 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
                         void* dh, int64_t dh_batch, int Nt, int Nd, const FftPlan& plan, const void* tw,
                         double scale, hipStream_t st) {
     if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
-    const int lp = 0;  // one sensor per workgroup: its partial sums are one contiguous run
-    dim3 grid(Nd, nb), block(kFftThreads);
-    const size_t lds = fft_lds_bytes(plan.N, lp, r);
+    const int twl = twl_of(plan.N, r);
+    dim3 grid(Nd, nb), block(kFftThreads);  // one sensor per workgroup
+    const size_t lds = fft_lds_bytes(plan.N, 0, r);
     PtrBatch none{};
     const PtrBatch& d = dout ? *dout : none;
     if (r == Real::F32) {
         if (dout)
             k_dside<float, false><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,
-                                                            (cx<float>*)dh, dh_batch, Nt, Nd, plan, lp,
-                                                            (const cx<float>*)tw, (float)scale);
+                                                            (cx<float>*)dh, dh_batch, Nt, Nd, plan,
+                                                            (const cx<float>*)tw, twl, (float)scale);
         else
             k_dside<float, true><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,
-                                                           (cx<float>*)dh, dh_batch, Nt, Nd, plan, lp,
-                                                           (const cx<float>*)tw, (float)scale);
+                                                           (cx<float>*)dh, dh_batch, Nt, Nd, plan,
+                                                           (const cx<float>*)tw, twl, (float)scale);
     } else {
         if (dout)
             k_dside<double, false><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,
-                                                             (cx<double>*)dh, dh_batch, Nt, Nd, plan, lp,
-                                                             (const cx<double>*)tw, scale);
+                                                             (cx<double>*)dh, dh_batch, Nt, Nd, plan,
+                                                             (const cx<double>*)tw, twl, scale);
         else
             k_dside<double, true><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,
-                                                            (cx<double>*)dh, dh_batch, Nt, Nd, plan, lp,
-                                                            (const cx<double>*)tw, scale);
+                                                            (cx<double>*)dh, dh_batch, Nt, Nd, plan,
+                                                            (const cx<double>*)tw, twl, scale);
     }
     return hipGetLastError();
 }

@@ -25,7 +25,7 @@ enum class Real { F32, F64 };
 enum class Stor { C128 = 0, C64 = 1, BF16 = 2 };
 
 // Threads per workgroup of every FFT kernel.
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 512;
 
 // Columns per FFT workgroup (power of two, log2) for a transform of half-length N in
 // real type `r`; 0 columns (returns -1) when N does not fit one workgroup.

@@ -1,0 +1,81 @@
+"""Continuous batching on the GPU: every request's result in a mixed, overlapping stream of
+requests equals the same request run alone (within the FP32 tolerance; bitwise where the
+same kernels run), and CG solves reach their residual (checked with the FP64 oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2407_13066_amd.serving import GpuExecutor, Request, Server, percentile
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {"A": (32, 8, 512), "B": (48, 10, 1000), "C": (64, 20, 3000)}
+
+
+def build_ops(bt, rng):
+    blocks = {n: rng.standard_normal(s) * np.exp(-np.arange(s[0]) / (s[0] / 7))[:, None, None]
+              for n, s in SHAPES.items()}
+    return blocks, {n: bt.btoep_create(b, "f32") for n, b in blocks.items()}
+
+
+def solo(bt, op, req):
+    if req.kind == "F":
+        return bt.btoep_apply_F(op, req.x)
+    if req.kind == "FT":
+        return bt.btoep_apply_FT(op, req.x)
+    if req.kind == "H":
+        return bt.btoep_apply_H(op, req.x, req.noise_prec, req.prior_prec)
+    x = torch.empty_like(req.x)
+    cg = bt.btoep_cg_start(op, req.x, x, req.rtol, req.noise_prec, req.prior_prec)
+    p, ap = cg.p_ptr, cg.ap_ptr
+    for it in range(req.max_iter):
+        bt.btoep_apply_batched_ptrs(op, "H", [cg.p(r) for r in range(req.k)], [cg.ap(r) for r in range(req.k)],
+                                    req.noise_prec, req.prior_prec)
+        bt.btoep_cg_update(cg)
+        bt.btoep_cg_poll(cg)
+        torch.cuda.synchronize()
+        ready, active, iters, _ = bt.btoep_cg_status(cg)
+        if ready and active == 0:
+            break
+    cg.end()
+    return x
+
+
+def test_mixed_requests_equal_solo_runs(bt):
+    rng = np.random.default_rng(61)
+    gen = torch.Generator(device="cuda").manual_seed(61)
+    blocks, ops = build_ops(bt, rng)
+    ex = GpuExecutor(ops, n_streams=2, max_batch=16)
+    srv = Server(ex, hbm_budget=1 << 30, max_batch=16, n_streams=2, poll_every=2)
+    arrivals = []
+    kinds = ["F", "FT", "H", "CG"]
+    for i in range(48):
+        name = "ABC"[i % 3]
+        Nt, Nd, Nm = SHAPES[name]
+        kind = kinds[(i // 3) % 4]
+        k = int(rng.integers(1, 7))
+        x = torch.randn((k, Nt, Nd if kind == "FT" else Nm), generator=gen, device="cuda")
+        arrivals.append((0.0005 * i, Request(rid=i, op=name, kind=kind, x=x, noise_prec=1.0, prior_prec=1.0,
+                                             rtol=1e-6, max_iter=200)))
+    torch.cuda.synchronize()
+    done = srv.run(arrivals, timeout=300)
+    torch.cuda.synchronize()
+    assert len(done) == 48 and srv.used == 0
+    assert srv.launches < sum(1 for _, r in arrivals if r.kind != "CG") + sum(r.iters for _, r in arrivals)
+    for _, req in arrivals:
+        ref = solo(bt, ops[req.op], req)
+        torch.cuda.synchronize()
+        got, want = req.out.double().cpu().numpy(), ref.double().cpu().numpy()
+        if req.kind == "CG":
+            assert req.converged, req
+            b = req.x.double().cpu().numpy()
+            for r in range(req.k):
+                Hx = oracle.apply_H(blocks[req.op], got[r], 1.0, 1.0)
+                assert np.linalg.norm(b[r] - Hx) / np.linalg.norm(b[r]) <= 1e-5
+                assert oracle.rel_l2(got[r], want[r]) <= 1e-4
+        else:
+            for r in range(req.k):
+                assert oracle.rel_l2(got[r], want[r]) <= 1e-5, (req.kind, req.k)
+    lat = [r.latency for r in done]
+    assert 0 < percentile(lat, 50) <= percentile(lat, 99)
