@@ -56,6 +56,58 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
+def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, check_cols=1):
+    """H applies with k stacked right-hand sides on the FP32- and BF16-stored operator
+    (matrix-core products); per-right-hand-side time against the single-vector H, matrix-core
+    throughput of the products, and the error of sampled columns against the FP64 oracle."""
+    import torch
+    import oracle
+    import synth
+    Nt, Nd, Nm = blocks.shape
+    out = {}
+    for storage in ("f32", "bf16"):
+        op = op32 if storage == "f32" else bt.btoep_create(blocks, "bf16")
+        res = {}
+        for k in ks:
+            M = torch.from_numpy(synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=np.float32)).cuda()
+            HM = torch.empty_like(M)
+            ws = torch.empty(bt.btoep_workspace_size(op, "H", k), dtype=torch.uint8, device="cuda")
+            bt.btoep_apply_H(op, M, 1.0, 1.0, out=HM, ws=ws)
+            torch.cuda.synchronize()
+            bt.btoep_profile_enable(op, True)
+            reps = 3
+            t = time.perf_counter()
+            for _ in range(reps):
+                bt.btoep_apply_H(op, M, 1.0, 1.0, out=HM, ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / reps
+            prof = bt.btoep_profile_read(op)
+            bt.btoep_profile_enable(op, False)
+            flops = 8.0 * (Nt + 1) * Nd * Nm * k  # one product pass
+            kern = {}
+            for name in ("sbgemv_n", "sbgemv_c"):
+                if name in prof:
+                    avg = prof[name][1] / prof[name][0]
+                    kern[name] = {"avg_ms": round(avg, 3), "TFLOPs": round(flops / (avg * 1e-3) / 1e12, 1)}
+            errs = []
+            if k == ks[0]:
+                Mh = M[:check_cols].double().cpu().numpy()
+                Fm = oracle.apply_F(blocks, Mh)
+                ref = oracle.apply_FT(blocks, Fm) + Mh
+                got = HM[:check_cols].double().cpu().numpy()
+                errs = [oracle.rel_l2(got[r], ref[r]) for r in range(check_cols)]
+            res["k%d" % k] = {"ms": round(ms, 3), "ms_per_rhs": round(ms / k, 4),
+                              "gain_vs_k1": round(h1_ms / (ms / k), 2), "products": kern,
+                              **({"rel_err_sampled": errs} if errs else {})}
+            log("multi-RHS %s k=%d: %.2f ms (%.3f ms/RHS, x%.1f vs k=1)" % (storage, k, ms, ms / k, h1_ms / (ms / k)))
+            del M, HM, ws
+            torch.cuda.empty_cache()
+        out[storage] = res
+        if op is not op32:
+            op.destroy()
+    return out
+
+
 def serving_benchmark(bt, n_req, rates, seed=13066):
     """Continuous-batching server over the three resident serving operators (FP32 storage):
     a burst measures capacity, then Poisson arrivals at fractions of it give p50 / p99
@@ -146,6 +198,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (for scaling PMC byte counters)")
+    ap.add_argument("--multi-rhs", default="8,32,64",
+                    help="comma-separated right-hand-side counts for the stacked-H measurement ('' skips it)")
     ap.add_argument("--serving-requests", type=int, default=150,
                     help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
@@ -160,6 +216,21 @@ def main():
     import synth
     import paper_2407_13066_amd as bt
     from paper_2407_13066_amd import build as btbuild
+
+    if args.calibrate_copy:
+        n = 1 << 30  # 4 GiB of float32 read and 4 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / 5
+        print(json.dumps({"calibration": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "ms": round(dt * 1e3, 4), "GBs_read_plus_write": round(8 * n / dt / 1e9, 1)}))
+        return 0
 
     if not os.path.exists(bt.LIB_PATH):
         btbuild.build()
@@ -301,6 +372,10 @@ def main():
                                                 ns, Nm, runs, t / runs,
                                                 "" if ns == Nm else ", scaled x%.0f (cost is linear in Nm)" % (Nm / ns))}
         log("cpu oracle %.2f s per H" % per)
+
+    if args.multi_rhs:
+        ks = [int(v) for v in args.multi_rhs.split(",") if v]
+        result["multi_rhs"] = multi_rhs_benchmark(bt, blocks, op, ks, ms_per_step)
 
     if args.serving_requests > 0:
         op.destroy()

@@ -158,6 +158,9 @@ struct Dft<7, DIR, T> : DftOdd<7, DIR, T> {};
 // the last butterfly redo the last one and do not store), so all of a thread's LDS and
 // twiddle reads can be in flight together.
 // Dynamic LDS of every FFT kernel: data (N+1) x P complex, then (when staged) the twiddles.
+// The kernels ask for four waves per SIMD (two 512-thread workgroups per CU): measured faster
+// than full-register single-workgroup occupancy although the passes then keep some state in
+// scratch.
 extern __shared__ __align__(16) unsigned char fft_smem[];
 
 // Each pass is its own (non-inlined) function so that register allocation is per radix;
@@ -339,7 +342,7 @@ __device__ __forceinline__ void stage_real_rows(T* shr, const Tin* __restrict__ 
 // ----------------------------------------------------------------------------------------
 // Forward: x (real, Nt rows) -> X (N+1 complex rows).
 template <typename T, typename Tin, typename So>
-__global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
                                                          int64_t out_row, int64_t out_batch, int Nt, int ncols,
                                                          FftPlan plan, int logP, const cx<T>* __restrict__ twg,
                                                          int twl) {
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(PtrBatch in, int64_t
 
 // Setup form (operator block column, FP64 in, batch over rows s with explicit strides).
 template <typename So>
-__global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c_strided(const double* __restrict__ in, int64_t in_row,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_r2c_strided(const double* __restrict__ in, int64_t in_row,
                                                                  int64_t in_batch, So* __restrict__ out,
                                                                  int64_t out_row, int64_t out_batch, int Nt,
                                                                  int ncols, FftPlan plan, int logP,
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c_strided(const double
 
 // Inverse: X (N+1 complex rows) -> x_j for j < Nt, times out_scale, plus add_scale * addend.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(const cx<T>* __restrict__ in, int64_t in_row,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_c2r(const cx<T>* __restrict__ in, int64_t in_row,
                                                          int64_t in_batch, PtrBatch out, int64_t out_row,
                                                          PtrBatch add, T add_scale, int Nt, int ncols,
                                                          FftPlan plan, int logP, const cx<T>* __restrict__ twg,
@@ -443,7 +446,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(const cx<T>* __restr
 // then either store d (F) or zero-pad, forward transform and store the bins (H).  One
 // sensor (column) per workgroup, whose partial sums part[b][s][f][span] are contiguous.
 template <typename T, bool HMODE>
-__global__ __launch_bounds__(kFftThreads, 2) void k_dside(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_dside(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
                                                        PtrBatch dout, cx<T>* __restrict__ dh, int64_t dh_batch,
                                                        int Nt, int Nd, FftPlan plan, const cx<T>* __restrict__ twg,
                                                        int twl, T scale) {
