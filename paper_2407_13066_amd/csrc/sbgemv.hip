@@ -53,21 +53,28 @@ struct StorT<bf16c> {
     }
 };
 
-// 32 bytes of the operator (VEC complex entries) as two 16-byte loads; non-temporal when NTL.
+// 16 bytes of the operator; non-temporal when NTL.
 template <bool NTL>
-__device__ __forceinline__ void load32(const void* p, u32x4* w) {
+__device__ __forceinline__ u32x4 load16(const void* p) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
-    if (NTL) {
-        w[0] = __builtin_nontemporal_load(q);
-        w[1] = __builtin_nontemporal_load(q + 1);
-    } else {
-        w[0] = q[0];
-        w[1] = q[1];
-    }
+    return NTL ? __builtin_nontemporal_load(q) : *q;
 }
 
 constexpr int kGemvThreads = 256;
 constexpr int kGemvWaves = kGemvThreads / kWave;
+
+// Lane data layout.  A wave covers a tile of 64 x VEC columns (2 KB of one operator row) as
+// two 1 KB chunks; in chunk h lane l owns the CPL = 16 / sizeof(S) columns starting at
+// h * 64 * CPL + l * CPL, so every load instruction reads one fully contiguous 1 KB run.
+// Element v of a lane (v = h * CPL + e) is StorT<S>::get(w, v) with w[h] the chunk's load.
+template <typename S>
+struct Lanes {
+    static constexpr int CPL = 16 / (int)sizeof(S);
+    static constexpr int VEC = StorT<S>::VEC;
+    static constexpr int NCH = VEC / CPL;  // 2
+    __device__ static int col(int lane, int v) { return (v / CPL) * kWave * CPL + lane * CPL + (v % CPL); }
+    __device__ static int chunk(int lane, int h) { return h * kWave * CPL + lane * CPL; }
+};
 
 // ---- N direction ----------------------------------------------------------------------
 // Wave w owns row blocks s0 = RB (w + 4 j); for each it walks the span in tiles of 64 lanes x
@@ -82,7 +89,8 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__
                                                            cx<typename StorT<S>::A>* __restrict__ part,
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
     typedef typename StorT<S>::A A;
-    constexpr int VEC = StorT<S>::VEC;
+    typedef Lanes<S> LN;
+    constexpr int VEC = LN::VEC, CPL = LN::CPL, NCH = LN::NCH;
     constexpr int TILE = kWave * VEC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<A>* msh = reinterpret_cast<cx<A>*>(smem_raw);
@@ -91,6 +99,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__
     const int col0 = span * CS;
     const int ncol = min(CS, Nm - col0);
     const cx<A>* __restrict__ mrow = mh + (int64_t)b * mh_batch + (int64_t)f * ldv + col0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < CS; i += kGemvThreads) msh[i] = (i < ncol) ? mrow[i] : cx<A>{0, 0};
     __syncthreads();
 
@@ -100,20 +109,24 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__
     const int nrb = (first < Nd) ? (Nd - first + kGemvWaves * RB - 1) / (kGemvWaves * RB) : 0;
     const int total = nrb * ntile;
     if (total == 0) return;
-    // last VEC-aligned column group that lies inside the padded row (loads are clamped to it;
-    // the staged vector is zero past ncol, so clamped lanes add nothing)
-    const int last_col = ((ncol + VEC - 1) / VEC) * VEC - VEC;
+    // last chunk start inside the row (chunks past ncol are clamped to it; the staged vector
+    // is zero past ncol, so their products add nothing)
+    const int last_chunk = ((ncol - 1) / CPL) * CPL;
     const S* __restrict__ Ff = Fh + (int64_t)f * Nd * ldF + col0;
     cx<A>* __restrict__ pout = part + (int64_t)b * part_batch + (int64_t)f * nspan + span;
     const int64_t pstride = (int64_t)nfreq * nspan;
 
-    u32x4 wa[RB][2], wb[RB][2];
+    u32x4 wa[RB][NCH], wb[RB][NCH];
     int ij = 0, it = 0;  // issue pointer (row block, tile)
-    auto issue = [&](u32x4(&w)[RB][2]) {
+    auto issue = [&](u32x4(&w)[RB][NCH]) {
         const int s0 = first + ij * kGemvWaves * RB;
-        const int col = min((it * kWave + lane) * VEC, last_col);
+        const int base = it * TILE;
 #pragma unroll
-        for (int r = 0; r < RB; ++r) load32<NTL>(Ff + (int64_t)min(s0 + r, Nd - 1) * ldF + col, w[r]);
+        for (int r = 0; r < RB; ++r) {
+            const S* row = Ff + (int64_t)min(s0 + r, Nd - 1) * ldF;
+#pragma unroll
+            for (int h = 0; h < NCH; ++h) w[r][h] = load16<NTL>(row + min(base + LN::chunk(lane, h), last_chunk));
+        }
         if (++it == ntile) {
             it = 0;
             ++ij;
@@ -123,11 +136,11 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = cx<A>{0, 0};
     int cj = 0, ct = 0;  // consume pointer
-    auto consume = [&](const u32x4(&w)[RB][2]) {
-        const int col = (ct * kWave + lane) * VEC;
+    auto consume = [&](const u32x4(&w)[RB][NCH]) {
+        const int base = ct * TILE;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            const cx<A> mv = msh[col + v];
+            const cx<A> mv = msh[base + LN::col(lane, v)];
 #pragma unroll
             for (int r = 0; r < RB; ++r) cfma(acc[r], StorT<S>::get(w[r], v), mv);
         }
@@ -155,9 +168,9 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_n(const S* __restrict__
 }
 
 // ---- C direction ----------------------------------------------------------------------
-// Lanes own VEC consecutive columns; rows are consumed RB at a time with the next RB rows'
-// loads already in flight.  dh_f is staged in LDS zero-padded to a multiple of 2 RB rows
-// (rows past Nd load row Nd-1 and are multiplied by zero).
+// Each wave owns a tile of 64 x VEC columns; rows are consumed RB at a time with the next RB
+// rows' loads already in flight.  dh_f is staged in LDS zero-padded to a multiple of 2 RB
+// rows (rows past Nd load row Nd-1 and are multiplied by zero).
 constexpr int kDChunk = 1024;
 
 template <typename S, int RB, bool NTL>
@@ -167,13 +180,22 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
                                                            cx<typename StorT<S>::A>* __restrict__ mo, int64_t ldv,
                                                            int64_t mo_batch) {
     typedef typename StorT<S>::A A;
-    constexpr int VEC = StorT<S>::VEC;
+    typedef Lanes<S> LN;
+    constexpr int VEC = LN::VEC, CPL = LN::CPL, NCH = LN::NCH;
     __shared__ cx<A> dsh[kDChunk];
     const int f = blockIdx.y, b = blockIdx.z;
-    const int col = (blockIdx.x * kGemvThreads + threadIdx.x) * VEC;
-    const bool active = col < Nm;
-    const int colc = min(col, ((Nm + VEC - 1) / VEC) * VEC - VEC);
-    const S* __restrict__ Ff = Fh + (int64_t)f * Nd * ldF + colc;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int tile0 = (blockIdx.x * kGemvWaves + wave) * kWave * VEC;
+    const int last_chunk = ((Nm - 1) / CPL) * CPL;
+    int cofs[NCH];
+    bool valid[NCH];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+        const int c = tile0 + LN::chunk(lane, h);
+        valid[h] = c < Nm;
+        cofs[h] = min(c, last_chunk);
+    }
+    const S* __restrict__ Ff = Fh + (int64_t)f * Nd * ldF;
     const cx<A>* __restrict__ dv = dh + (int64_t)b * dh_batch + (int64_t)f * Nd;
     cx<A> acc[VEC];
 #pragma unroll
@@ -185,12 +207,16 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
         __syncthreads();
         for (int i = threadIdx.x; i < nsp; i += kGemvThreads) dsh[i] = (i < ns) ? dv[c0 + i] : cx<A>{0, 0};
         __syncthreads();
-        u32x4 wa[RB][2], wb[RB][2];
-        auto issue = [&](int s, u32x4(&w)[RB][2]) {
+        u32x4 wa[RB][NCH], wb[RB][NCH];
+        auto issue = [&](int s, u32x4(&w)[RB][NCH]) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r) load32<NTL>(Ff + (int64_t)min(c0 + s + r, Nd - 1) * ldF, w[r]);
+            for (int r = 0; r < RB; ++r) {
+                const S* row = Ff + (int64_t)min(c0 + s + r, Nd - 1) * ldF;
+#pragma unroll
+                for (int h = 0; h < NCH; ++h) w[r][h] = load16<NTL>(row + cofs[h]);
+            }
         };
-        auto consume = [&](int s, const u32x4(&w)[RB][2]) {
+        auto consume = [&](int s, const u32x4(&w)[RB][NCH]) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const cx<A> d = dsh[s + r];
@@ -206,10 +232,12 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
             consume(s + RB, wb);
         }
     }
-    if (active) {
-        cx<A>* __restrict__ o = mo + (int64_t)b * mo_batch + (int64_t)f * ldv + col;
+    cx<A>* __restrict__ o = mo + (int64_t)b * mo_batch + (int64_t)f * ldv;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) o[v] = acc[v];
+    for (int h = 0; h < NCH; ++h) {
+        if (!valid[h]) continue;
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) o[tile0 + LN::chunk(lane, h) + e] = acc[h * CPL + e];
     }
 }
 
