@@ -113,7 +113,8 @@ def serving_benchmark(bt, n_req, rates, seed=13066):
     a burst measures capacity, then Poisson arrivals at fractions of it give p50 / p99
     latency and right-hand-side applies per second.  Request mix: kind uniform over
     F / FT / H / CG, operator uniform, k uniform in 1..16; H and CG use noise_prec = 1e4,
-    prior_prec = 1e-3; CG stops at relative residual 1e-6 (at most 500 iterations)."""
+    prior_prec = 1e-3; CG right-hand sides are b = 1e4 F^T y (the inverse problem's form, y ~ N(0,1)
+    data vectors) and CG stops at relative residual 1e-6 (at most 500 iterations)."""
     import torch
     import synth
     from paper_2407_13066_amd.serving import GpuExecutor, Request, Server, percentile
@@ -137,7 +138,12 @@ def serving_benchmark(bt, n_req, rates, seed=13066):
         op = ops[name]
         kind = kinds[int(rng.integers(4))]
         k = int(rng.integers(1, 17))
-        x = torch.randn((k, op.Nt, op.Nd if kind == "FT" else op.Nm), generator=gen, device="cuda")
+        if kind == "CG":
+            # inverse-problem right-hand side b = sigma^-2 F^T y (y a data vector)
+            y = torch.randn((k, op.Nt, op.Nd), generator=gen, device="cuda")
+            x = bt.btoep_apply_FT(op, y).mul_(1e4)
+        else:
+            x = torch.randn((k, op.Nt, op.Nd if kind == "FT" else op.Nm), generator=gen, device="cuda")
         return Request(rid=rid, op=name, kind=kind, x=x, noise_prec=1e4, prior_prec=1e-3, rtol=1e-6, max_iter=500)
 
     def run(arrivals):
