@@ -47,6 +47,25 @@ def algorithmic_bytes(Nt, Nd, Nm, nfreq, nspan, sb, vb):
     }
 
 
+def measured_traffic(kernel, variant):
+    """HBM bytes per launch of `kernel` (variant id) from the committed rocprofv3 counter summary,
+    or None when that summary is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sbgemv_fp32_nt420_nd100_nm65536_hbm_traffic.md")
+    try:
+        text = open(path).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(block)
+        csrc = os.path.join(ROOT, "paper_2407_13066_amd", "csrc")
+        src = hashlib.sha256(open(os.path.join(csrc, "sbgemv.hip"), "rb").read() +
+                             open(os.path.join(csrc, "common.h"), "rb").read()).hexdigest()
+        if src != data["source_sha256"]:
+            return None
+        return data["variants"]["%s/%d" % (kernel, variant)]["traffic_bytes"]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -313,6 +332,8 @@ def main():
     dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
     dom_avg_s = kern[dom][1] / kern[dom][0] * 1e-3
     achieved = ab[dom] / dom_avg_s / 1e9
+    traffic = measured_traffic(dom, tune["var_n"] if dom == "sbgemv_n" else tune["var_c"]) \
+        if dom in ("sbgemv_n", "sbgemv_c") else None
 
     result = {
         "metric": "H matvecs/s + HBM GB/s (% of peak) at stated rel err; serving p50/p99 ms",
@@ -337,7 +358,9 @@ def main():
         "kernels": kernels,
         "autotune": tune,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes": ab[dom],
+                     "traffic": traffic, "traffic_GBs": round(traffic / dom_avg_s / 1e9, 1) if traffic else None},
     }
 
     if not args.no_check:

@@ -8,6 +8,7 @@ Requests arrive over time, each naming a resident operator, a kind (``F``, ``FT`
 * forms, every scheduling round, batches per (operator, pipeline, scalars) out of whatever is
   ready: new apply requests and the next H application of every in-flight CG solve, up to
   ``max_batch`` right-hand sides per launch (pointer-array applies, so nothing is copied);
+  batches with one-shot applies are launched before batches made only of CG iterations;
 * launches the batches on several streams, so batches of different operators overlap on the
   device, and enqueues each CG request's vector updates right behind its batch;
 * notices completions without blocking (events, asynchronous CG residual polls) and
@@ -156,7 +157,13 @@ class Server:
                 pipe = req.kind
             key = (req.op, pipe, req.noise_prec if pipe == "H" else 0.0, req.prior_prec if pipe == "H" else 0.0)
             groups.setdefault(key, []).append(req)
-        return groups
+        # groups holding one-shot applies go first (oldest arrival first), then groups made only
+        # of CG iterations: a long solve must not hold short requests behind it
+        def rank(item):
+            reqs = item[1]
+            only_cg = all(r.kind == "CG" for r in reqs)
+            return (only_cg, min(r.t_arrival for r in reqs))
+        return collections.OrderedDict(sorted(groups.items(), key=rank))
 
     def _launch(self):
         for (op, pipe, noise, prior), reqs in self._ready_items().items():
