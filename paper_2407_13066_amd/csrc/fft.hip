@@ -233,6 +233,83 @@ __device__ __forceinline__ void fft_lds(const FftPlan& plan, int logP, bool twl,
         fft_passes<T, DIR, CMAX, false>(plan, logP, tw_off, twg);
 }
 
+// ---- compile-time plans ---------------------------------------------------------------
+// For the transform lengths of the common workloads the passes are instantiated with N, Ns
+// and R as constants and inlined: no per-pass calls, constant strides and modulo, twiddles
+// read from LDS.  Any other length runs the runtime plan above.
+struct RuntimePlan {
+    static constexpr bool kStatic = false;
+};
+template <int... Rs>
+struct CtPlan {
+    static constexpr bool kStatic = true;
+    static constexpr int N = (Rs * ... * 1);
+};
+
+template <typename T, int R, int DIR, int CMAX, int N, int Ns>
+__device__ __forceinline__ void ct_pass(int logP, size_t tw_off) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(fft_smem + tw_off);
+    constexpr int MAXB = (CMAX + R - 1) / R;
+    constexpr int NR = N / R;
+    constexpr int stride = NR / Ns;
+    const int nbf = NR << logP;
+    const int P1 = (1 << logP) - 1;
+    const int tid = threadIdx.x;
+    cx<T> v[MAXB][R];
+#pragma unroll
+    for (int bb = 0; bb < MAXB; ++bb) {
+        const int g = min(tid + bb * kFftThreads, nbf - 1);
+        const int c = g & P1, j = g >> logP;
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[bb][r] = sh[((j + r * NR) << logP) + c];
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[2 * (k * r * stride)];
+                if (DIR > 0) w.im = -w.im;
+                v[bb][r] = cmul(v[bb][r], w);
+            }
+        }
+        Dft<R, DIR, T>::run(v[bb]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < MAXB; ++bb) {
+        const int g = tid + bb * kFftThreads;
+        if (g < nbf) {
+            const int c = g & P1, j = g >> logP;
+            const int k = j % Ns;
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) sh[((base + r * Ns) << logP) + c] = v[bb][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int DIR, int CMAX, int N, int Ns, int R, int... Rest>
+__device__ __forceinline__ void ct_passes(int logP, size_t tw_off) {
+    ct_pass<T, R, DIR, CMAX, N, Ns>(logP, tw_off);
+    if constexpr (sizeof...(Rest) > 0) ct_passes<T, DIR, CMAX, N, Ns * R, Rest...>(logP, tw_off);
+}
+
+template <typename T, int DIR, int CMAX, int... Rs>
+__device__ __forceinline__ void ct_run(CtPlan<Rs...>, int logP, size_t tw_off) {
+    ct_passes<T, DIR, CMAX, CtPlan<Rs...>::N, 1, Rs...>(logP, tw_off);
+}
+
+// Static plans require the twiddles in LDS (the launchers only pick them then).
+template <typename T, int DIR, int CMAX, typename PL>
+__device__ __forceinline__ void run_fft(const FftPlan& plan, int logP, bool twl, size_t tw_off,
+                                        const cx<T>* __restrict__ twg) {
+    if constexpr (PL::kStatic)
+        ct_run<T, DIR, CMAX>(PL{}, logP, tw_off);
+    else
+        fft_lds<T, DIR, CMAX>(plan, logP, twl, tw_off, twg);
+}
+
 template <typename T>
 struct FftCfg;
 template <>
@@ -339,23 +416,32 @@ __device__ __forceinline__ void stage_real_rows(T* shr, const Tin* __restrict__ 
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  When the
+// column-block count divides by 8, XCD x is given the contiguous range of column blocks
+// [x nbx/8, (x+1) nbx/8) in order, so neighbouring column blocks -- which share 128-byte lines
+// of every time and frequency row -- meet in the same L2.
+__device__ __forceinline__ int column_block() {
+    const int nbx = gridDim.x, bx = blockIdx.x;
+    return (nbx & 7) ? bx : (bx & 7) * (nbx >> 3) + (bx >> 3);
+}
+
 // ----------------------------------------------------------------------------------------
 // Forward: x (real, Nt rows) -> X (N+1 complex rows).
-template <typename T, typename Tin, typename So>
+template <typename T, typename Tin, typename So, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
                                                          int64_t out_row, int64_t out_batch, int Nt, int ncols,
                                                          FftPlan plan, int logP, const cx<T>* __restrict__ twg,
                                                          int twl) {
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const int N = plan.N, P = 1 << logP;
-    const int col0 = blockIdx.x << logP;
+    const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
     const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const Tin* __restrict__ x = static_cast<const Tin*>(in.p[blockIdx.y]);
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
     stage_real_rows<T, Tin>(reinterpret_cast<T*>(fft_smem), x, in_row, Nt, N, logP, col0, ncols);
     __syncthreads();
-    fft_lds<T, -1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
+    run_fft<T, -1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
         if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
@@ -371,7 +457,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
                                                                  const cx<double>* __restrict__ twg, int twl) {
     cx<double>* sh = reinterpret_cast<cx<double>*>(fft_smem);
     const int N = plan.N, P = 1 << logP;
-    const int col0 = blockIdx.x << logP;
+    const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<double>);
     const cx<double>* tw = stage_twiddles<double>(tw_off, twl, N, twg);
     const double* __restrict__ x = in + (int64_t)blockIdx.y * in_batch;
@@ -386,7 +472,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 }
 
 // Inverse: X (N+1 complex rows) -> x_j for j < Nt, times out_scale, plus add_scale * addend.
-template <typename T>
+template <typename T, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_c2r(const cx<T>* __restrict__ in, int64_t in_row,
                                                          int64_t in_batch, PtrBatch out, int64_t out_row,
                                                          PtrBatch add, T add_scale, int Nt, int ncols,
@@ -395,7 +481,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const T* shr = reinterpret_cast<const T*>(fft_smem);
     const int N = plan.N, P = 1 << logP, P1 = P - 1;
-    const int col0 = blockIdx.x << logP;
+    const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
     const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const cx<T>* __restrict__ y = in + (int64_t)blockIdx.y * in_batch;
@@ -420,7 +506,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     __syncthreads();
     c2r_split<T>(sh, N, logP, tw);
     __syncthreads();
-    fft_lds<T, 1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
+    run_fft<T, 1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     const int nout = Nt << logP;
     for (int e0 = 0; e0 < nout; e0 += kLoadUnroll * kFftThreads) {
         T av[kLoadUnroll];
@@ -445,7 +531,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 // Data side: reduce split partial sums over spans, inverse transform, keep j < Nt, scale;
 // then either store d (F) or zero-pad, forward transform and store the bins (H).  One
 // sensor (column) per workgroup, whose partial sums part[b][s][f][span] are contiguous.
-template <typename T, bool HMODE>
+template <typename T, bool HMODE, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_dside(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
                                                        PtrBatch dout, cx<T>* __restrict__ dh, int64_t dh_batch,
                                                        int Nt, int Nd, FftPlan plan, const cx<T>* __restrict__ twg,
@@ -469,7 +555,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     __syncthreads();
     c2r_split<T>(sh, N, logP, tw);
     __syncthreads();
-    fft_lds<T, 1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
+    run_fft<T, 1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     if (!HMODE) {
         T* __restrict__ d = static_cast<T*>(const_cast<void*>(dout.p[blockIdx.y]));
         for (int j = threadIdx.x; j < Nt; j += kFftThreads) d[(int64_t)j * Nd + s] = scale * shr[j];
@@ -478,7 +564,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     // keep samples j < Nt (scaled), zero the padding, transform forward again
     for (int j = threadIdx.x; j < 2 * N; j += kFftThreads) shr[j] = (j < Nt) ? scale * shr[j] : (T)0;
     __syncthreads();
-    fft_lds<T, -1, FftCfg<T>::CMAX>(plan, logP, twl, tw_off, twg);
+    run_fft<T, -1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     cx<T>* __restrict__ o = dh + (int64_t)blockIdx.y * dh_batch;
     for (int f = threadIdx.x; f <= N; f += kFftThreads) o[(int64_t)f * Nd + s] = r2c_bin(sh, N, logP, f, 0, tw);
 }
@@ -518,6 +604,39 @@ static int pick_log_cols(int N, Real r, int ncols, int nb) {
     return lp;
 }
 
+// Index of the compile-time plan equal to `plan` (FP32 kernels with LDS twiddles), or -1.
+typedef CtPlan<8, 4> Plan32;
+typedef CtPlan<8, 8> Plan64;
+typedef CtPlan<8, 8, 2> Plan128;
+typedef CtPlan<8, 8, 4> Plan256;
+typedef CtPlan<4, 5, 3, 7> Plan420;
+typedef CtPlan<8, 8, 8> Plan512;
+#define BT_STATIC_PLANS(X) \
+    X(0, Plan32)           \
+    X(1, Plan64)           \
+    X(2, Plan128)          \
+    X(3, Plan256)          \
+    X(4, Plan420)          \
+    X(5, Plan512)
+
+template <int... Rs>
+static bool same_plan(const FftPlan& p, CtPlan<Rs...>) {
+    const int rs[] = {Rs...};
+    if (p.npass != (int)sizeof...(Rs)) return false;
+    for (int i = 0; i < p.npass; ++i)
+        if (p.radix[i] != rs[i]) return false;
+    return true;
+}
+
+static int static_plan_id(const FftPlan& p, Real r) {
+    if (r != Real::F32 || !twl_of(p.N, r)) return -1;
+#define BT_MATCH(ID, PLAN) \
+    if (same_plan(p, PLAN{})) return ID;
+    BT_STATIC_PLANS(BT_MATCH)
+#undef BT_MATCH
+    return -1;
+}
+
 hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_row, int nb, void* out,
                           int64_t out_row, int64_t out_batch, int Nt, int ncols, const FftPlan& plan,
                           const void* tw, hipStream_t st) {
@@ -526,16 +645,25 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
     const int twl = twl_of(plan.N, r);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
-    if (r == Real::F32 && ir == Real::F32 && os == Stor::C64)
-        k_fft_r2c<float, float, cx<float>><<<grid, block, lds, st>>>(in, in_row, (cx<float>*)out, out_row,
-                                                                     out_batch, Nt, ncols, plan, lp,
-                                                                     (const cx<float>*)tw, twl);
-    else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128)
-        k_fft_r2c<double, double, cx<double>><<<grid, block, lds, st>>>(in, in_row, (cx<double>*)out, out_row,
-                                                                        out_batch, Nt, ncols, plan, lp,
-                                                                        (const cx<double>*)tw, twl);
-    else
+    if (r == Real::F32 && ir == Real::F32 && os == Stor::C64) {
+#define BT_R2C(PLAN)                                                                                       \
+    k_fft_r2c<float, float, cx<float>, PLAN><<<grid, block, lds, st>>>(in, in_row, (cx<float>*)out, out_row, \
+                                                                       out_batch, Nt, ncols, plan, lp,      \
+                                                                       (const cx<float>*)tw, twl)
+        switch (static_plan_id(plan, r)) {
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_R2C(PLAN); break;
+            BT_STATIC_PLANS(BT_CASE)
+#undef BT_CASE
+            default: BT_R2C(RuntimePlan); break;
+        }
+#undef BT_R2C
+    } else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128) {
+        k_fft_r2c<double, double, cx<double>, RuntimePlan><<<grid, block, lds, st>>>(
+            in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, plan, lp, (const cx<double>*)tw, twl);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -573,14 +701,24 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
     const int twl = twl_of(plan.N, r);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
-    if (r == Real::F32)
-        k_fft_c2r<float><<<grid, block, lds, st>>>((const cx<float>*)in, in_row, in_batch, out, out_row, add,
-                                                   (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw, twl,
-                                                   (float)out_scale);
-    else
-        k_fft_c2r<double><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out, out_row, add,
-                                                    add_scale, Nt, ncols, plan, lp, (const cx<double>*)tw, twl,
-                                                    out_scale);
+    if (r == Real::F32) {
+#define BT_C2R(PLAN)                                                                                            \
+    k_fft_c2r<float, PLAN><<<grid, block, lds, st>>>((const cx<float>*)in, in_row, in_batch, out, out_row, add, \
+                                                     (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw, \
+                                                     twl, (float)out_scale)
+        switch (static_plan_id(plan, r)) {
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_C2R(PLAN); break;
+            BT_STATIC_PLANS(BT_CASE)
+#undef BT_CASE
+            default: BT_C2R(RuntimePlan); break;
+        }
+#undef BT_C2R
+    } else {
+        k_fft_c2r<double, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out,
+                                                                 out_row, add, add_scale, Nt, ncols, plan, lp,
+                                                                 (const cx<double>*)tw, twl, out_scale);
+    }
     return hipGetLastError();
 }
 
@@ -594,23 +732,39 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
     PtrBatch none{};
     const PtrBatch& d = dout ? *dout : none;
     if (r == Real::F32) {
-        if (dout)
-            k_dside<float, false><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,
-                                                            (cx<float>*)dh, dh_batch, Nt, Nd, plan,
-                                                            (const cx<float>*)tw, twl, (float)scale);
-        else
-            k_dside<float, true><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,
-                                                           (cx<float>*)dh, dh_batch, Nt, Nd, plan,
-                                                           (const cx<float>*)tw, twl, (float)scale);
+#define BT_DS(MODE, PLAN)                                                                                     \
+    k_dside<float, MODE, PLAN><<<grid, block, lds, st>>>((const cx<float>*)part, nspan, part_batch, d,        \
+                                                         (cx<float>*)dh, dh_batch, Nt, Nd, plan, (const cx<float>*)tw, \
+                                                         twl, (float)scale)
+        switch (static_plan_id(plan, r)) {
+#define BT_CASE(ID, PLAN)       \
+    case ID:                    \
+        if (dout)               \
+            BT_DS(false, PLAN); \
+        else                    \
+            BT_DS(true, PLAN);  \
+        break;
+            BT_STATIC_PLANS(BT_CASE)
+#undef BT_CASE
+            default:
+                if (dout)
+                    BT_DS(false, RuntimePlan);
+                else
+                    BT_DS(true, RuntimePlan);
+                break;
+        }
+#undef BT_DS
     } else {
         if (dout)
-            k_dside<double, false><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,
-                                                             (cx<double>*)dh, dh_batch, Nt, Nd, plan,
-                                                             (const cx<double>*)tw, twl, scale);
+            k_dside<double, false, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)part, nspan,
+                                                                          part_batch, d, (cx<double>*)dh,
+                                                                          dh_batch, Nt, Nd, plan,
+                                                                          (const cx<double>*)tw, twl, scale);
         else
-            k_dside<double, true><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,
-                                                            (cx<double>*)dh, dh_batch, Nt, Nd, plan,
-                                                            (const cx<double>*)tw, twl, scale);
+            k_dside<double, true, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)part, nspan,
+                                                                         part_batch, d, (cx<double>*)dh,
+                                                                         dh_batch, Nt, Nd, plan,
+                                                                         (const cx<double>*)tw, twl, scale);
     }
     return hipGetLastError();
 }

@@ -51,9 +51,10 @@ def test_every_pin_through_the_gpu_path(bt):
 
 # shapes: ragged Nm (not a multiple of 8 or of a span), Nd not a multiple of the row block,
 # Nt whose transform length needs padding beyond 2 Nt (11 -> N 12), primes, several
-# FFT column tiles and several spans
+# FFT column tiles and several spans, and every transform length with a compile-time plan
+# (N = 32, 64, 128, 256, 420, 512) next to runtime-plan lengths
 RAGGED = [(1, 1, 1), (2, 3, 5), (11, 5, 13), (13, 7, 1000), (37, 9, 300), (64, 100, 4099), (45, 3, 9001),
-          (128, 50, 2000), (17, 130, 257)]
+          (128, 50, 2000), (17, 130, 257), (512, 3, 700), (256, 12, 333), (420, 5, 1111)]
 
 
 @pytest.mark.parametrize("shape", RAGGED)
