@@ -165,8 +165,17 @@ def serving_benchmark(bt, n_req, rates, seed=13066):
             x = torch.randn((k, op.Nt, op.Nd if kind == "FT" else op.Nm), generator=gen, device="cuda")
         return Request(rid=rid, op=name, kind=kind, x=x, noise_prec=1e4, prior_prec=1e-3, rtol=1e-6, max_iter=500)
 
-    def run(arrivals):
-        ex = GpuExecutor(ops, n_streams=2, max_batch=32)
+    # graphs for every batch shape the server can form, captured before any timing
+    ex_graph = GpuExecutor(ops, n_streams=2, max_batch=32, use_graphs=True)
+    ex_eager = GpuExecutor(ops, n_streams=2, max_batch=32, use_graphs=False)
+    t0 = time.perf_counter()
+    ex_graph.prepare_graphs([(n, p, nz, pr) for n in "ABC" for p, nz, pr in
+                             (("F", 0.0, 0.0), ("FT", 0.0, 0.0), ("H", 1e4, 1e-3))], range(1, 33))
+    capture_s = time.perf_counter() - t0
+    log("captured %d serving graphs in %.2f s" % (len(ex_graph.graphs), capture_s))
+    launch_cost = graph_launch_benchmark(bt, ops, ex_graph, ex_eager)
+
+    def run(arrivals, ex=ex_graph):
         srv = Server(ex, hbm_budget=48 << 30, max_batch=32, n_streams=2, poll_every=4)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -188,6 +197,8 @@ def serving_benchmark(bt, n_req, rates, seed=13066):
     capacity = cap["requests_per_s"]
     log("serving capacity (burst of %d): %.1f requests/s" % (len(burst), capacity))
     out = {"operators": {n: list(shapes[i]) for i, n in enumerate("ABC")}, "storage": "c64",
+           "graphs": {"count": len(ex_graph.graphs), "capture_s": round(capture_s, 2),
+                      "per_apply_ms": launch_cost},
            "capacity_requests_per_s": capacity, "burst": cap, "rates": {}}
     last = None
     for frac in rates:
@@ -200,6 +211,13 @@ def serving_benchmark(bt, n_req, rates, seed=13066):
         out["rates"]["%.2fx" % frac] = res
         log("serving at %.2fx capacity: p50 %.2f ms, p99 %.2f ms, %.0f RHS-applies/s" % (
             frac, res["p50_ms"], res["p99_ms"], res["rhs_applies_per_s"]))
+        if last is None:
+            # the same arrivals with batches launched kernel by kernel instead of graph replays
+            _, _, res_e = run([(t, Request(rid=r.rid, op=r.op, kind=r.kind, x=r.x, noise_prec=r.noise_prec,
+                                           prior_prec=r.prior_prec, rtol=r.rtol, max_iter=r.max_iter))
+                               for t, r in arrivals], ex=ex_eager)
+            out["rates"]["%.2fx_no_graphs" % frac] = res_e
+            log("  same arrivals without graphs: p50 %.2f ms, p99 %.2f ms" % (res_e["p50_ms"], res_e["p99_ms"]))
         last = done
     # the same request alone: a few requests of the last run, rerun one by one
     worst = 0.0
@@ -211,8 +229,104 @@ def serving_benchmark(bt, n_req, rates, seed=13066):
         a, b = req.out.double(), ref.double()
         worst = max(worst, float(torch.linalg.norm(a - b) / torch.linalg.norm(b)))
     out["mixed_vs_alone_max_rel_diff"] = worst
+    ex_graph.close()
     for op in ops.values():
         op.destroy()
+    return out
+
+
+def graph_launch_benchmark(bt, ops, ex_graph, ex_eager, reps=200):
+    """Per-apply time of back-to-back applies on one stream: pointer-array applies launched
+    kernel by kernel, against replays of the captured graph with its address table rewritten
+    every replay (as the server does) and without (as a solver's iteration does)."""
+    import torch
+    out = {}
+    for name, op in ops.items():
+        for pipe, k in (("H", 1), ("H", 8), ("F", 1)):
+            n_in = op.Nd if pipe == "FT" else op.Nm
+            n_out = op.Nd if pipe == "F" else op.Nm
+            x = torch.randn((k, op.Nt, n_in), device="cuda")
+            y = torch.empty((k, op.Nt, n_out), device="cuda")
+            ins = [x[r].data_ptr() for r in range(k)]
+            outs = [y[r].data_ptr() for r in range(k)]
+            noise, prior = (1e4, 1e-3) if pipe == "H" else (0.0, 0.0)
+            st = ex_graph.streams[0]
+            g = ex_graph._graph(name, pipe, noise, prior, k, 0)
+            res = {}
+            for mode in ("eager", "graph", "graph_same_vectors"):
+                def once():
+                    if mode == "graph":
+                        g.launch(ins, outs, stream=st)
+                    elif mode == "graph_same_vectors":
+                        g.launch(stream=st)
+                    else:
+                        bt.btoep_apply_batched_ptrs(op, pipe, ins, outs, noise, prior, ws=ex_eager.ws[name][0],
+                                                    stream=st)
+                for _ in range(5):
+                    once()
+                torch.cuda.synchronize()
+                reps_op = max(10, min(reps, int(2e9 / max(op.info["fhat_bytes"], 1))))
+                t0 = time.perf_counter()
+                for _ in range(reps_op):
+                    once()
+                torch.cuda.synchronize()
+                res[mode] = round((time.perf_counter() - t0) * 1e3 / reps_op, 4)
+            out["%s_%s_k%d" % (name, pipe, k)] = res
+            log("apply %s %s k=%d: %.4f ms eager, %.4f ms graph, %.4f ms graph on the same vectors" % (
+                name, pipe, k, res["eager"], res["graph"], res["graph_same_vectors"]))
+            del x, y
+    return out
+
+
+def cg_benchmark(bt):
+    """Inverse-problem CG: H = sigma^-2 F^T F + alpha I with sigma = 1e-2, alpha = 1e-3 on
+    Nt=256, Nd=64, Nm=16384 (blocks N(0,1) exp(-k/(Nt/7))), d = F m_true + N(0, sigma^2),
+    b = sigma^-2 F^T d, to a true relative residual of 1e-8: all-FP64 CG against FP32-inner
+    CG with FP64 iterative refinement, each with inner iterations replayed from a graph and
+    launched kernel by kernel.  b is formed with the FP64 operator on the device."""
+    import torch
+    import synth
+    w = synth.WORKLOADS["cg-nt256-nd64-nm16384"]
+    Nt, Nd, Nm = w["Nt"], w["Nd"], w["Nm"]
+    sigma, alpha = w["sigma"], w["alpha"]
+    blocks = synth.blocks(Nt, Nd, Nm, w["tau"])
+    hi = bt.btoep_create(blocks, "f64")
+    lo = bt.btoep_create(blocks, "f32")
+    del blocks
+    for op in (hi, lo):
+        bt.btoep_autotune(op, reps=3)
+    m_true = torch.from_numpy(synth.vectors(1, Nt, Nm, synth.STREAM_MTRUE)).cuda()
+    noise = torch.from_numpy(synth.vectors(1, Nt, Nd, synth.STREAM_NOISE)).cuda()
+    dobs = bt.btoep_apply_F(hi, m_true) + sigma * noise
+    b = bt.btoep_apply_FT(hi, dobs).mul_(sigma ** -2)
+    out = {"workload": "cg-nt256-nd64-nm16384", "sigma": sigma, "alpha": alpha, "rtol": w["rtol"]}
+    sols = {}
+    for name, op_lo, op_hi, inner_rtol in (("fp64", hi, None, 1e-9), ("fp32_refined", lo, hi, 1e-5)):
+        for use_graph in (True, False):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, res = bt.btoep_cg_solve(op_lo, op_hi, b, x, sigma ** -2, alpha, rtol=w["rtol"], max_outer=20,
+                                        max_inner=5000, inner_rtol=inner_rtol, check_every=8, use_graph=use_graph)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            r = res[0]
+            key = name + ("" if use_graph else "_no_graph")
+            out[key] = {"status": st, "seconds": round(sec, 4), "inner_iters": r["inner_iters"],
+                        "outer_iters": r["outer_iters"], "matvecs": r["matvecs"],
+                        "true_rel_residual": r["rel_residual"],
+                        "ms_per_matvec": round(sec * 1e3 / max(r["matvecs"], 1), 4)}
+            sols[key] = x
+            log("cg %s: %.3f s, %d inner + %d outer, true rel residual %.2e" % (
+                key, sec, r["inner_iters"], r["outer_iters"], r["rel_residual"]))
+    # the two solutions agree in the data space (null-space parts are not determined)
+    Fd = bt.btoep_apply_F(hi, sols["fp32_refined"] - sols["fp64"])
+    out["data_space_rel_diff"] = float(torch.linalg.norm(Fd) / torch.linalg.norm(bt.btoep_apply_F(hi, sols["fp64"])))
+    out["graph_equals_no_graph"] = bool(torch.equal(sols["fp64"], sols["fp64_no_graph"]) and
+                                        torch.equal(sols["fp32_refined"], sols["fp32_refined_no_graph"]))
+    out["speedup_refined_vs_fp64"] = round(out["fp64"]["seconds"] / out["fp32_refined"]["seconds"], 2)
+    hi.destroy()
+    lo.destroy()
     return out
 
 
@@ -229,6 +343,7 @@ def main():
                     help="comma-separated right-hand-side counts for the stacked-H measurement ('' skips it)")
     ap.add_argument("--serving-requests", type=int, default=150,
                     help="requests per arrival rate in the serving run (0 skips it)")
+    ap.add_argument("--no-cg", action="store_true", help="skip the CG solve measurement")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
                     help="parameter columns of the operator the CPU oracle is timed on")
     args = ap.parse_args()
@@ -406,10 +521,13 @@ def main():
         ks = [int(v) for v in args.multi_rhs.split(",") if v]
         result["multi_rhs"] = multi_rhs_benchmark(bt, blocks, op, ks, ms_per_step)
 
-    if args.serving_requests > 0:
-        op.destroy()
-        del blocks
+    op.destroy()
+    del blocks
+    torch.cuda.empty_cache()
+    if not args.no_cg:
+        result["cg"] = cg_benchmark(bt)
         torch.cuda.empty_cache()
+    if args.serving_requests > 0:
         result["serving"] = serving_benchmark(bt, args.serving_requests, rates=(0.5, 0.9))
 
     print(json.dumps(result), flush=True)

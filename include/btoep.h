@@ -134,12 +134,37 @@ btoep_status btoep_apply_batched(btoep_op op, btoep_which which, int64_t k, cons
                                  void* const* out, double noise_prec, double prior_prec, void* ws, size_t ws_bytes,
                                  void* stream);
 
+/*
+ * Graph form of one apply, for callers that repeat the same step on new vectors (a server's
+ * batches, a solver's iterations): the launches of btoep_apply_batched for k <=
+ * BTOEP_MAX_BATCH right-hand sides are recorded once into a HIP graph and replayed by
+ * btoep_graph_launch.  The vector addresses are not frozen into the graph: the kernels read
+ * them from a device table the graph owns, which btoep_graph_launch rewrites (with a small
+ * kernel on `stream`, right before the replay) from
+ *   in[r], out[r]  (HOST arrays of k device pointers, as for btoep_apply_batched; both NULL
+ *                   to replay on the previous launch's vectors).
+ * For _H no output may overlap an input.  `ws` (caller owned, at least
+ * btoep_workspace_size(op, which, k) bytes, required) and the operator are used by every
+ * replay and must outlive the graph.  Launches of one graph must be ordered on one stream
+ * (they share the table and the workspace).  Creation allocates the table and launches
+ * nothing; destruction synchronises the device.  The results equal btoep_apply_batched's.
+ */
+typedef struct btoep_graph_s* btoep_graph;
+
+btoep_status btoep_graph_create(btoep_op op, btoep_which which, int64_t k, double noise_prec, double prior_prec,
+                                void* ws, size_t ws_bytes, btoep_graph* out);
+btoep_status btoep_graph_launch(btoep_graph g, const void* const* in, void* const* out, void* stream);
+btoep_status btoep_graph_destroy(btoep_graph g);
+
 typedef struct {
     double rtol;        /* stop when ||b - H x||_2 <= rtol ||b||_2 (true residual, FP64)       */
     int max_outer;      /* refinement steps (outer loop)                                        */
     int max_inner;      /* CG iterations per refinement step                                    */
     double inner_rtol;  /* inner CG stops when its recurrence residual drops by this factor     */
     int check_every;    /* inner iterations between host convergence checks (>= 1)             */
+    int use_graph;      /* != 0: each inner iteration (H apply, inner products, vector
+                           updates) is captured once per call into a HIP graph and replayed;
+                           same kernels and results as launching them one by one            */
 } btoep_cg_opts;
 
 typedef struct {

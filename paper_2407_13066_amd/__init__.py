@@ -43,7 +43,7 @@ class _Info(ctypes.Structure):
 
 class CgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
-                ("inner_rtol", ctypes.c_double), ("check_every", ctypes.c_int)]
+                ("inner_rtol", ctypes.c_double), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class CgResult(ctypes.Structure):
@@ -80,6 +80,9 @@ def load_library(path=LIB_PATH):
         "btoep_apply_H": ([vp, i64, dbl, dbl, vp, vp, vp, sz, vp], st),
         "btoep_apply_batched": ([vp, ctypes.c_int, i64, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, dbl, vp, sz,
                                  vp], st),
+        "btoep_graph_create": ([vp, ctypes.c_int, i64, dbl, dbl, vp, sz, ctypes.POINTER(vp)], st),
+        "btoep_graph_launch": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], st),
+        "btoep_graph_destroy": ([vp], st),
         "btoep_cg_solve": ([vp, vp, i64, dbl, dbl, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp,
                             sz, vp], st),
         "btoep_autotune": ([vp, ctypes.c_int, vp, ctypes.POINTER(TuneResult)], st),
@@ -288,9 +291,11 @@ def btoep_apply_batched(op, which, ins, outs, noise_prec=1.0, prior_prec=1.0, ws
 
 
 def btoep_cg_solve(op_lo, op_hi, b, x, noise_prec, prior_prec, rtol=1e-8, max_outer=10, max_inner=1000,
-                   inner_rtol=1e-4, check_every=4, ws=None, stream=None, raise_on_not_converged=False):
+                   inner_rtol=1e-4, check_every=4, ws=None, stream=None, raise_on_not_converged=False,
+                   use_graph=True):
     """Solve H x = b (FP64 b, x of shape [k][Nt][Nm] on the device; x is the initial guess).
 
+    ``use_graph`` replays each inner iteration from a captured HIP graph.
     Returns (status, [CgResult per right-hand side]).
     """
     torch = _torch()
@@ -299,7 +304,7 @@ def btoep_cg_solve(op_lo, op_hi, b, x, noise_prec, prior_prec, rtol=1e-8, max_ou
             raise ValueError("%s must be a contiguous float64 CUDA tensor" % n)
     b3 = b if b.dim() == 3 else b.unsqueeze(0)
     k = b3.shape[0]
-    opts = CgOpts(rtol, max_outer, max_inner, inner_rtol, check_every)
+    opts = CgOpts(rtol, max_outer, max_inner, inner_rtol, check_every, 1 if use_graph else 0)
     res = (CgResult * k)()
     wp, wn = _ws(ws)
     st = load_library().btoep_cg_solve(op_lo.handle, op_hi.handle if op_hi is not None else None, k,
@@ -414,3 +419,51 @@ def btoep_apply_batched_ptrs(op, which, in_ptrs, out_ptrs, noise_prec=1.0, prior
     _check(load_library().btoep_apply_batched(op.handle, WHICH[which], k, PA(*in_ptrs), PA(*out_ptrs),
                                               float(noise_prec), float(prior_prec), wp, wn, _stream(stream)),
            "btoep_apply_batched", op.handle)
+
+
+class ApplyGraph:
+    """One apply of k right-hand sides captured into a HIP graph (btoep_graph_*).
+
+    ``launch(in_ptrs, out_ptrs)`` points the replay at other vectors (device addresses, ints);
+    without them it reuses the previous ones.  All launches of one graph must go to one
+    stream (they share the graph's address table and the workspace).
+    """
+
+    def __init__(self, op, which, k, noise_prec=1.0, prior_prec=1.0, ws=None):
+        torch = _torch()
+        k = int(k)
+        if not 1 <= k <= MAX_BATCH:
+            raise ValueError("k must be in 1..%d" % MAX_BATCH)
+        self.op, self.which, self.k = op, which, k
+        if ws is None:
+            ws = torch.empty(btoep_workspace_size(op, which, k), dtype=torch.uint8,
+                             device=torch.device("cuda", op.info["device"]))
+        self.ws = ws
+        self.handle = None
+        self._arr = ctypes.c_void_p * k
+        h = ctypes.c_void_p()
+        wp, wn = _ws(ws)
+        _check(load_library().btoep_graph_create(op.handle, WHICH[which], k, float(noise_prec), float(prior_prec),
+                                                 wp, wn, ctypes.byref(h)), "btoep_graph_create", op.handle)
+        self.handle = h
+
+    def launch(self, in_ptrs=None, out_ptrs=None, stream=None):
+        if in_ptrs is None:
+            pin = pout = None
+        else:
+            if len(in_ptrs) != self.k or len(out_ptrs) != self.k:
+                raise ValueError("graph holds %d right-hand sides" % self.k)
+            pin, pout = self._arr(*in_ptrs), self._arr(*out_ptrs)
+        _check(load_library().btoep_graph_launch(self.handle, pin, pout, _stream(stream)), "btoep_graph_launch",
+               self.op.handle)
+
+    def destroy(self):
+        if self.handle:
+            load_library().btoep_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -199,10 +199,13 @@ hipEvent_t pool_event(btoep_op op) {
     return e;
 }
 
+// Set while this thread records launches into a graph: no timing events are recorded then.
+thread_local bool g_capturing = false;
+
 // Launch `fn` on `st`, bracketed by events when profiling is on.
 template <typename Fn>
 hipError_t timed(btoep_op op, int kid, hipStream_t st, Fn&& fn) {
-    if (!op->prof) return fn();
+    if (!op->prof || g_capturing) return fn();
     hipEvent_t a = pool_event(op), b = pool_event(op);
     if (!a || !b) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(a, st);
@@ -302,6 +305,44 @@ btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& i
     BT_HIP(op, timed(op, K_C2R_M, st, [&] {
         return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, none, 0.0, Nt, Nm, op->plan, tw, inv_n, st);
     }));
+    return BTOEP_OK;
+}
+
+// An instantiated graph and the graph it came from.
+struct GraphHolder {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    GraphHolder() = default;
+    GraphHolder(const GraphHolder&) = delete;
+    GraphHolder& operator=(const GraphHolder&) = delete;
+    ~GraphHolder() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+// Records the launches `fn(stream)` makes on a private stream into a graph and instantiates
+// it.  Nothing runs during the capture; the graph is launched later on any stream.
+template <typename Fn>
+btoep_status capture_graph(btoep_op op, GraphHolder& h, Fn&& fn) {
+    hipStream_t cs = nullptr;
+    BT_HIP(op, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    btoep_status s = BTOEP_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        g_capturing = true;
+        s = fn(cs);
+        g_capturing = false;
+        const hipError_t e2 = hipStreamEndCapture(cs, &h.g);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && s == BTOEP_OK) e = hipGraphInstantiate(&h.x, h.g, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (s != BTOEP_OK) return s;
+    if (e != hipSuccess) {
+        set_err(op, "graph capture", e);
+        return BTOEP_ERR_HIP;
+    }
     return BTOEP_OK;
 }
 
@@ -528,6 +569,91 @@ btoep_status btoep_apply_batched(btoep_op op, btoep_which which, int64_t k, cons
     return run_apply(op, which, (int)k, pi, po, noise_prec, prior_prec, (char*)ws, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+struct btoep_graph_s {
+    btoep_op op = nullptr;
+    int k = 0;
+    const void** table = nullptr;  // device: k input addresses, then k output addresses
+    GraphHolder h;
+    ~btoep_graph_s() {
+        if (table) (void)hipFree(table);
+    }
+};
+
+namespace {
+
+// Writes a replay's addresses into the graph's table (one lane per right-hand side).
+__global__ void k_write_table(PtrBatch in, PtrBatch out, int k, const void** table) {
+    const int r = threadIdx.x;
+    if (r < k) {
+        table[r] = in.p[r];
+        table[k + r] = out.p[r];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+btoep_status btoep_graph_create(btoep_op op, btoep_which which, int64_t k, double noise_prec, double prior_prec,
+                                void* ws, size_t ws_bytes, btoep_graph* out) {
+    if (!out) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!op || k < 1 || k > kMaxBatch || !ws) return BTOEP_ERR_INVALID_ARG;
+    if (which != BTOEP_APPLY_F && which != BTOEP_APPLY_FT && which != BTOEP_APPLY_H) return BTOEP_ERR_INVALID_ARG;
+    if (ws_bytes < apply_layout(op, which, k).total) return BTOEP_ERR_WORKSPACE_TOO_SMALL;
+    btoep_graph gr = new (std::nothrow) btoep_graph_s();
+    if (!gr) return BTOEP_ERR_OUT_OF_MEMORY;
+    gr->op = op;
+    gr->k = (int)k;
+    DeviceGuard g(op->device);
+    hipError_t e = hipMalloc((void**)&gr->table, 2 * (size_t)k * sizeof(void*));
+    if (e != hipSuccess) {
+        set_err(op, "graph table", e);
+        delete gr;
+        return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+    }
+    PtrBatch pi{}, po{};
+    pi.dev = gr->table;
+    po.dev = gr->table + k;
+    const btoep_status s = capture_graph(op, gr->h, [&](hipStream_t cs) {
+        return run_apply(op, which, (int)k, pi, po, noise_prec, prior_prec, (char*)ws, cs);
+    });
+    if (s != BTOEP_OK) {
+        delete gr;
+        return s;
+    }
+    *out = gr;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_graph_launch(btoep_graph gr, const void* const* in, void* const* out, void* stream) {
+    if (!gr || (!in) != (!out)) return BTOEP_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceGuard g(gr->op->device);
+    if (in) {
+        PtrBatch pi{}, po{};
+        for (int r = 0; r < gr->k; ++r) {
+            if (!in[r] || !out[r]) return BTOEP_ERR_INVALID_ARG;
+            pi.p[r] = in[r];
+            po.p[r] = out[r];
+        }
+        k_write_table<<<1, kMaxBatch, 0, st>>>(pi, po, gr->k, gr->table);
+        BT_HIP(gr->op, hipGetLastError());
+    }
+    BT_HIP(gr->op, hipGraphLaunch(gr->h.x, st));
+    return BTOEP_OK;
+}
+
+btoep_status btoep_graph_destroy(btoep_graph gr) {
+    if (!gr) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(gr->op->device);
+    (void)hipDeviceSynchronize();  // no replay may still be running
+    delete gr;
+    return BTOEP_OK;
+}
+
 btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_prec, double prior_prec,
                             const double* b, double* x, const btoep_cg_opts* opts, btoep_cg_result* results, void* ws,
                             size_t ws_bytes, void* stream) {
@@ -538,7 +664,7 @@ btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_pr
     if (hi && (hi->storage != BTOEP_F64 || hi->Nt != lo->Nt || hi->Nd != lo->Nd || hi->Nm != lo->Nm ||
                hi->device != lo->device))
         return BTOEP_ERR_INVALID_ARG;
-    btoep_cg_opts o{1e-8, 10, 1000, 1e-4, 4};
+    btoep_cg_opts o{1e-8, 10, 1000, 1e-4, 4, 1};
     if (opts) o = *opts;
     if (!(o.rtol > 0) || o.max_outer < 1 || o.max_inner < 1 || !(o.inner_rtol > 0) || o.check_every < 1)
         return BTOEP_ERR_INVALID_ARG;
@@ -576,6 +702,19 @@ btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_pr
     BT_HIP(lo, hipMemcpyAsync(sc, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, st));
     BT_HIP(lo, launch_dot(Real::F64, b, b, n, nb, n, sc, kScBB, 0, tmp, st));
 
+    // One inner CG iteration: Ap = H_lo p, then the FP64 scalar recurrences and vector
+    // updates.  With opts.use_graph it is captured once per call and replayed.
+    auto inner_step = [&](hipStream_t s1) -> btoep_status {
+        const btoep_status q = apply_contig(lo, BTOEP_APPLY_H, k, p, Ap, noise_prec, prior_prec, aws, aws_bytes, s1);
+        if (q != BTOEP_OK) return q;
+        BT_HIP(lo, launch_dot(rl, p, Ap, n, nb, n, sc, kScPAP, kScPAP, tmp, s1));
+        BT_HIP(lo, launch_cg_xr(rl, rl, e, r, p, Ap, n, nb, n, sc, s1));
+        BT_HIP(lo, launch_dot(rl, r, r, n, nb, n, sc, kScRRN, kScRRN, tmp, s1));
+        BT_HIP(lo, launch_cg_p(rl, p, r, n, nb, n, sc, s1));
+        return BTOEP_OK;
+    };
+    GraphHolder step;
+
     int outer = 0, inner_total = 0, matvecs = 0;
     const double rtol2 = o.rtol * o.rtol;
     bool all_conv = false;
@@ -599,15 +738,19 @@ btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_pr
         BT_HIP(lo, launch_axpbz(rl, p, 1.0, rl, r, 0.0, rl, nullptr, n, nb, n, st));
         BT_HIP(lo, launch_dot(rl, r, r, n, nb, n, sc, kScRR, 0, tmp, st));
         BT_HIP(lo, launch_cg_init_scalars(sc, nb, o.inner_rtol * o.inner_rtol, rtol2, st));
-        for (int it = 0; it < o.max_inner; ++it) {
-            s = apply_contig(lo, BTOEP_APPLY_H, k, p, Ap, noise_prec, prior_prec, aws, aws_bytes, stream);
+        if (o.use_graph && !step.x) {
+            s = capture_graph(lo, step, inner_step);
             if (s != BTOEP_OK) return s;
+        }
+        for (int it = 0; it < o.max_inner; ++it) {
+            if (step.x) {
+                BT_HIP(lo, hipGraphLaunch(step.x, st));
+            } else {
+                s = inner_step(st);
+                if (s != BTOEP_OK) return s;
+            }
             ++matvecs;
             ++inner_total;
-            BT_HIP(lo, launch_dot(rl, p, Ap, n, nb, n, sc, kScPAP, kScPAP, tmp, st));
-            BT_HIP(lo, launch_cg_xr(rl, rl, e, r, p, Ap, n, nb, n, sc, st));
-            BT_HIP(lo, launch_dot(rl, r, r, n, nb, n, sc, kScRRN, kScRRN, tmp, st));
-            BT_HIP(lo, launch_cg_p(rl, p, r, n, nb, n, sc, st));
             if ((it + 1) % o.check_every == 0) {
                 BT_HIP(lo, hipMemcpyAsync(hsc, sc, (size_t)nb * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
                 BT_HIP(lo, hipStreamSynchronize(st));

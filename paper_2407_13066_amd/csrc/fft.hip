@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
     const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
-    const Tin* __restrict__ x = static_cast<const Tin*>(in.p[blockIdx.y]);
+    const Tin* __restrict__ x = static_cast<const Tin*>(in.at(blockIdx.y));
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
     stage_real_rows<T, Tin>(reinterpret_cast<T*>(fft_smem), x, in_row, Nt, N, logP, col0, ncols);
     __syncthreads();
@@ -485,8 +485,8 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
     const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const cx<T>* __restrict__ y = in + (int64_t)blockIdx.y * in_batch;
-    T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.p[blockIdx.y]));
-    const T* __restrict__ a = static_cast<const T*>(add.p[blockIdx.y]);
+    T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.at(blockIdx.y)));
+    const T* __restrict__ a = static_cast<const T*>(add.at(blockIdx.y));
 
     const int total = (N + 1) << logP;
     for (int e0 = 0; e0 < total; e0 += kLoadUnroll * kFftThreads) {
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     __syncthreads();
     run_fft<T, 1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     if (!HMODE) {
-        T* __restrict__ d = static_cast<T*>(const_cast<void*>(dout.p[blockIdx.y]));
+        T* __restrict__ d = static_cast<T*>(const_cast<void*>(dout.at(blockIdx.y)));
         for (int j = threadIdx.x; j < Nt; j += kFftThreads) d[(int64_t)j * Nd + s] = scale * shr[j];
         return;
     }

@@ -15,10 +15,14 @@ struct FftPlan {
     int radix[kMaxPass];
 };
 
-// Up to kMaxBatch right-hand-side base pointers, passed by value as a kernel argument.
+// Up to kMaxBatch right-hand-side base pointers, passed by value as a kernel argument, or,
+// when `dev` is set, read by the kernels from that device array (so that a captured graph
+// can be replayed on other vectors by rewriting the array).
 constexpr int kMaxBatch = 64;
 struct PtrBatch {
     const void* p[kMaxBatch];
+    const void* const* dev = nullptr;
+    __host__ __device__ const void* at(int b) const { return dev ? dev[b] : p[b]; }
 };
 
 enum class Real { F32, F64 };
@@ -34,7 +38,7 @@ size_t fft_lds_bytes(int N, int logP, Real r);
 
 // ---- launchers (fft.hip) ------------------------------------------------------------
 // Forward real-to-complex transform of zero-padded columns.
-//   in  : batch b (b < nb) base in.p[b]; element (j, c) at [j * in_row + c], j < Nt, c < ncols
+//   in  : batch b (b < nb) base in.at(b); element (j, c) at [j * in_row + c], j < Nt, c < ncols
 //   out : complex, element (f, c) at out + b*out_batch + f*out_row + c, f <= N
 // Storage of `out` follows `os`; the compute precision is `r`.  Inputs of type `ir`.
 hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_row, int nb,
@@ -45,7 +49,7 @@ hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int
                                   void* out, int64_t out_row, int64_t out_batch, int Nt, int ncols,
                                   const FftPlan& plan, const void* tw64, hipStream_t st);
 // Inverse complex-to-real transform; keeps samples j < Nt:
-//   out[b][j][c] = out_scale * x_j  (+ add_scale * add[b][j][c] when add.p[0] != null)
+//   out[b][j][c] = out_scale * x_j  (+ add_scale * add[b][j][c] when `add` is present)
 hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_batch, int nb,
                           const PtrBatch& out, int64_t out_row, const PtrBatch& add, double add_scale,
                           int Nt, int ncols, const FftPlan& plan, const void* tw, double out_scale,

@@ -10,7 +10,9 @@ Requests arrive over time, each naming a resident operator, a kind (``F``, ``FT`
   ``max_batch`` right-hand sides per launch (pointer-array applies, so nothing is copied);
   batches with one-shot applies are launched before batches made only of CG iterations;
 * launches the batches on several streams, so batches of different operators overlap on the
-  device, and enqueues each CG request's vector updates right behind its batch;
+  device, and enqueues each CG request's vector updates right behind its batch; with graphs
+  on, a batch is one replay of a captured HIP graph for its (operator, pipeline, scalars,
+  size, stream), pointed at the batch's vectors through a device address table;
 * notices completions without blocking (events, asynchronous CG residual polls) and
   records arrival-to-completion latency.
 
@@ -230,18 +232,46 @@ def percentile(values, q):
 
 
 class GpuExecutor:
-    """Runs the server's batches with the HIP library (one workspace per operator and stream)."""
+    """Runs the server's batches with the HIP library (one workspace per operator and stream).
 
-    def __init__(self, ops, n_streams=2, max_batch=32):
+    With ``use_graphs`` every batch is a replay of a graph captured (on first use, or ahead of
+    time by ``prepare_graphs``) per (operator, pipeline, scalars, size, stream); otherwise the
+    pointer-array apply launches its kernels one by one.  Both run the same kernels.
+    """
+
+    def __init__(self, ops, n_streams=2, max_batch=32, use_graphs=True):
         import torch
         from . import btoep_workspace_size
         self.torch = torch
         self.ops = ops
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.use_graphs = bool(use_graphs)
+        self.graphs = {}
         self.ws = {}
         for name, op in ops.items():
             nb = btoep_workspace_size(op, "H", max_batch)
             self.ws[name] = [torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(n_streams)]
+
+    def _graph(self, op_name, pipe, noise, prior, k, stream_idx):
+        from . import ApplyGraph
+        key = (op_name, pipe, noise, prior, k, stream_idx)
+        g = self.graphs.get(key)
+        if g is None:
+            g = ApplyGraph(self.ops[op_name], pipe, k, noise, prior, ws=self.ws[op_name][stream_idx])
+            self.graphs[key] = g
+        return g
+
+    def prepare_graphs(self, pipes, ks):
+        """Capture ahead of time: ``pipes`` is a list of (operator, pipeline, noise, prior)."""
+        for op_name, pipe, noise, prior in pipes:
+            for k in ks:
+                for si in range(len(self.streams)):
+                    self._graph(op_name, pipe, noise, prior, k, si)
+
+    def close(self):
+        for g in self.graphs.values():
+            g.destroy()
+        self.graphs.clear()
 
     def request_bytes(self, req):
         op = self.ops[req.op]
@@ -286,7 +316,10 @@ class GpuExecutor:
                 rout = req.out.stride(0) * req.out.element_size()
                 ins += [req.x.data_ptr() + r * rin for r in range(req.k)]
                 outs += [req.out.data_ptr() + r * rout for r in range(req.k)]
-        btoep_apply_batched_ptrs(op, pipe, ins, outs, noise, prior, ws=self.ws[op_name][stream_idx], stream=st)
+        if self.use_graphs:
+            self._graph(op_name, pipe, noise, prior, len(ins), stream_idx).launch(ins, outs, stream=st)
+        else:
+            btoep_apply_batched_ptrs(op, pipe, ins, outs, noise, prior, ws=self.ws[op_name][stream_idx], stream=st)
         for req in batch:
             if req.kind == "CG":
                 btoep_cg_update(req._state, stream=st)

@@ -42,11 +42,12 @@ def solo(bt, op, req):
     return x
 
 
-def test_mixed_requests_equal_solo_runs(bt):
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_mixed_requests_equal_solo_runs(bt, use_graphs):
     rng = np.random.default_rng(61)
     gen = torch.Generator(device="cuda").manual_seed(61)
     blocks, ops = build_ops(bt, rng)
-    ex = GpuExecutor(ops, n_streams=2, max_batch=16)
+    ex = GpuExecutor(ops, n_streams=2, max_batch=16, use_graphs=use_graphs)
     srv = Server(ex, hbm_budget=1 << 30, max_batch=16, n_streams=2, poll_every=2)
     arrivals = []
     kinds = ["F", "FT", "H", "CG"]
@@ -80,3 +81,5 @@ def test_mixed_requests_equal_solo_runs(bt):
                 assert oracle.rel_l2(got[r], want[r]) <= 1e-5, (req.kind, req.k)
     lat = [r.latency for r in done]
     assert 0 < percentile(lat, 50) <= percentile(lat, 99)
+    assert (len(ex.graphs) > 0) == use_graphs
+    ex.close()
