@@ -386,35 +386,40 @@ __device__ __forceinline__ const cx<T>* stage_twiddles(size_t data_bytes, bool t
     return t;
 }
 
-// Real input rows j < Nt of P columns (zero rows j in [Nt, 2N)) into the packed LDS layout
-// z[n] = x[2n] + i x[2n+1]; loads are issued kLoadUnroll at a time with clamped addresses.
+// Real input rows j < Nt of one column tile (P columns) in the packed LDS layout
+// z[n] = x[2n] + i x[2n+1], zero rows j in [Nt, 2N).  `load` issues every global load of the
+// tile at once (FftCfg<T>::CMAX per thread cover the Nt P elements, which the LDS budget
+// bounds), with clamped addresses, before anything waits for them; `commit` writes them.
 template <typename T, typename Tin>
-__device__ __forceinline__ void stage_real_rows(T* shr, const Tin* __restrict__ x, int64_t in_row, int Nt, int N,
-                                                int logP, int col0, int ncols) {
-    const int P1 = (1 << logP) - 1;
-    const int total = Nt << logP;
-    for (int e = (Nt << logP) + threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
-        const int c = e & P1, j = e >> logP;
-        shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (T)0;
-    }
-    for (int e0 = 0; e0 < total; e0 += kLoadUnroll * kFftThreads) {
-        T val[kLoadUnroll];
+struct RealTile {
+    T v[FftCfg<T>::CMAX];
+    __device__ __forceinline__ void load(const Tin* __restrict__ x, int64_t in_row, int total, int logP, int col0,
+                                         int ncols) {
+        const int P1 = (1 << logP) - 1;
 #pragma unroll
-        for (int u = 0; u < kLoadUnroll; ++u) {
-            const int e = min(e0 + u * kFftThreads + (int)threadIdx.x, total - 1);
+        for (int u = 0; u < FftCfg<T>::CMAX; ++u) {
+            const int e = min(u * kFftThreads + (int)threadIdx.x, total - 1);
             const int c = e & P1, j = e >> logP;
-            val[u] = (T)x[(int64_t)j * in_row + min(col0 + c, ncols - 1)];
+            v[u] = (T)x[(int64_t)j * in_row + min(col0 + c, ncols - 1)];
+        }
+    }
+    __device__ __forceinline__ void commit(T* shr, int Nt, int N, int logP, int col0, int ncols) const {
+        const int P1 = (1 << logP) - 1;
+        const int total = Nt << logP;
+        for (int e = total + threadIdx.x; e < (2 * N) << logP; e += kFftThreads) {
+            const int c = e & P1, j = e >> logP;
+            shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (T)0;
         }
 #pragma unroll
-        for (int u = 0; u < kLoadUnroll; ++u) {
-            const int e = e0 + u * kFftThreads + (int)threadIdx.x;
+        for (int u = 0; u < FftCfg<T>::CMAX; ++u) {
+            const int e = u * kFftThreads + (int)threadIdx.x;
             if (e < total) {
                 const int c = e & P1, j = e >> logP;
-                shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (col0 + c < ncols) ? val[u] : (T)0;
+                shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (col0 + c < ncols) ? v[u] : (T)0;
             }
         }
     }
-}
+};
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  When the
 // column-block count divides by 8, XCD x is given the contiguous range of column blocks
@@ -436,10 +441,13 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int N = plan.N, P = 1 << logP;
     const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
-    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const Tin* __restrict__ x = static_cast<const Tin*>(in.at(blockIdx.y));
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
-    stage_real_rows<T, Tin>(reinterpret_cast<T*>(fft_smem), x, in_row, Nt, N, logP, col0, ncols);
+    // all input loads in flight before the twiddle copy waits for its own
+    RealTile<T, Tin> tile;
+    tile.load(x, in_row, Nt << logP, logP, col0, ncols);
+    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
+    tile.commit(reinterpret_cast<T*>(fft_smem), Nt, N, logP, col0, ncols);
     __syncthreads();
     run_fft<T, -1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
@@ -459,10 +467,12 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int N = plan.N, P = 1 << logP;
     const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<double>);
-    const cx<double>* tw = stage_twiddles<double>(tw_off, twl, N, twg);
     const double* __restrict__ x = in + (int64_t)blockIdx.y * in_batch;
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
-    stage_real_rows<double, double>(reinterpret_cast<double*>(fft_smem), x, in_row, Nt, N, logP, col0, ncols);
+    RealTile<double, double> tile;
+    tile.load(x, in_row, Nt << logP, logP, col0, ncols);
+    const cx<double>* tw = stage_twiddles<double>(tw_off, twl, N, twg);
+    tile.commit(reinterpret_cast<double*>(fft_smem), Nt, N, logP, col0, ncols);
     __syncthreads();
     fft_lds<double, -1, FftCfg<double>::CMAX>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
@@ -596,6 +606,11 @@ size_t fft_lds_bytes(int N, int logP, Real r) {
 
 static inline unsigned nblk(int n, int logP) { return (unsigned)((n + (1 << logP) - 1) >> logP); }
 
+// One batch of CMAX loads per thread covers a whole input tile (Nt P <= (N+1) P elements).
+static bool one_batch(int N, int logP, Real r) {
+    return ((int64_t)(N + 1) << logP) <= (int64_t)cmax_of(r) * kFftThreads;
+}
+
 // Narrow batches (the data side: Nd columns) get fewer columns per workgroup so that the
 // launch still spreads over the chip; wide ones keep the largest tile that fits.
 static int pick_log_cols(int N, Real r, int ncols, int nb) {
@@ -642,6 +657,7 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
                           const void* tw, hipStream_t st) {
     if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int lp = pick_log_cols(plan.N, r, ncols, nb);
+    if (!one_batch(plan.N, lp, r)) return hipErrorInvalidValue;
     const int twl = twl_of(plan.N, r);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
@@ -672,6 +688,7 @@ hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int
                                   const void* tw64, hipStream_t st) {
     if (fft_log_cols(plan.N, Real::F64) < 0 || nb <= 0) return hipErrorInvalidValue;
     const int lp = pick_log_cols(plan.N, Real::F64, ncols, nb);
+    if (!one_batch(plan.N, lp, Real::F64)) return hipErrorInvalidValue;
     const int twl = twl_of(plan.N, Real::F64);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, Real::F64);
