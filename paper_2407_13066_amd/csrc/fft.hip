@@ -493,25 +493,26 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int N = plan.N, P = 1 << logP, P1 = P - 1;
     const int col0 = column_block() << logP;
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
-    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     const cx<T>* __restrict__ y = in + (int64_t)blockIdx.y * in_batch;
     T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.at(blockIdx.y)));
     const T* __restrict__ a = static_cast<const T*>(add.at(blockIdx.y));
 
+    // every spectrum load of the tile in flight (one batch: the launcher checks that
+    // (N+1) P <= CMAX threads) before the twiddle copy waits for its own
+    constexpr int K = FftCfg<T>::CMAX;
     const int total = (N + 1) << logP;
-    for (int e0 = 0; e0 < total; e0 += kLoadUnroll * kFftThreads) {
-        cx<T> val[kLoadUnroll];
+    cx<T> val[K];
 #pragma unroll
-        for (int u = 0; u < kLoadUnroll; ++u) {
-            const int e = min(e0 + u * kFftThreads + (int)threadIdx.x, total - 1);
-            const int c = e & P1, f = e >> logP;
-            val[u] = y[(int64_t)f * in_row + min(col0 + c, ncols - 1)];
-        }
+    for (int u = 0; u < K; ++u) {
+        const int e = min(u * kFftThreads + (int)threadIdx.x, total - 1);
+        const int c = e & P1, f = e >> logP;
+        val[u] = y[(int64_t)f * in_row + min(col0 + c, ncols - 1)];
+    }
+    const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
 #pragma unroll
-        for (int u = 0; u < kLoadUnroll; ++u) {
-            const int e = e0 + u * kFftThreads + (int)threadIdx.x;
-            if (e < total) sh[e] = (col0 + (e & P1) < ncols) ? val[u] : cx<T>{0, 0};
-        }
+    for (int u = 0; u < K; ++u) {
+        const int e = u * kFftThreads + (int)threadIdx.x;
+        if (e < total) sh[e] = (col0 + (e & P1) < ncols) ? val[u] : cx<T>{0, 0};
     }
     __syncthreads();
     c2r_split<T>(sh, N, logP, tw);
@@ -715,6 +716,7 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
                           const FftPlan& plan, const void* tw, double out_scale, hipStream_t st) {
     if (fft_log_cols(plan.N, r) < 0 || nb <= 0 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int lp = pick_log_cols(plan.N, r, ncols, nb);
+    if (!one_batch(plan.N, lp, r)) return hipErrorInvalidValue;
     const int twl = twl_of(plan.N, r);
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, r);
