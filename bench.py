@@ -434,7 +434,7 @@ def main():
     FT_ms = time_call(lambda: bt.btoep_apply_FT(op, d, mt, ws=ws, stream=stream))
     log("F: %.3f ms, F^T: %.3f ms" % (F_ms, FT_ms))
 
-    nspan = -(-Nm // 4096)
+    nspan = -(-Nm // 4096)  # spans of the N-direction product at this shape (4096 columns each)
     ab = algorithmic_bytes(Nt, Nd, Nm, info["nfreq"], nspan, 8, 4)
     H_bytes = sum(ab.values())
     kernels = {}

@@ -109,7 +109,7 @@ size_t stor_bytes(Stor s) { return s == Stor::C128 ? 16 : (s == Stor::C64 ? 8 : 
 size_t vbytes(const btoep_op op) { return op->vreal == Real::F64 ? 8 : 4; }
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int64_t nspan_of(const btoep_op op) {
-    const int cs = sbgemv_n_span(op->stor, op->Nm);
+    const int cs = n_span_cols(op->stor, op->Nm, (int)op->nfreq);
     return (op->Nm + cs - 1) / cs;
 }
 

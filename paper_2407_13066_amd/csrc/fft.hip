@@ -386,18 +386,42 @@ __device__ __forceinline__ const cx<T>* stage_twiddles(size_t data_bytes, bool t
     return t;
 }
 
+// LDS a workgroup may use for one column tile plus the twiddle table.
+static constexpr size_t kFftLdsBudget = 64 * 1024;
+
+// Widest tile (log2 columns) the launchers pick for a compile-time plan of length N (twiddles
+// in LDS), and the global loads per thread that then cover one whole tile of N+1 rows.
+template <typename T>
+constexpr int ct_log_cols(int N) {
+    for (int lp = 6; lp >= 0; --lp) {
+        const size_t P = (size_t)1 << lp;
+        if ((size_t)(N + 1) * P * sizeof(cx<T>) + (size_t)2 * N * sizeof(cx<T>) <= kFftLdsBudget &&
+            (size_t)N * P <= (size_t)FftCfg<T>::CMAX * kFftThreads)
+            return lp;
+    }
+    return 0;
+}
+template <typename T, typename PL, bool STATIC = PL::kStatic>
+struct LoadSlots {
+    static constexpr int value = FftCfg<T>::CMAX;
+};
+template <typename T, typename PL>
+struct LoadSlots<T, PL, true> {
+    static constexpr int value = (((PL::N + 1) << ct_log_cols<T>(PL::N)) + kFftThreads - 1) / kFftThreads;
+};
+
 // Real input rows j < Nt of one column tile (P columns) in the packed LDS layout
 // z[n] = x[2n] + i x[2n+1], zero rows j in [Nt, 2N).  `load` issues every global load of the
-// tile at once (FftCfg<T>::CMAX per thread cover the Nt P elements, which the LDS budget
-// bounds), with clamped addresses, before anything waits for them; `commit` writes them.
-template <typename T, typename Tin>
+// tile at once (NL per thread cover the Nt P elements: the launchers check it), with clamped
+// addresses, before anything waits for them; `commit` writes them.
+template <typename T, typename Tin, int NL>
 struct RealTile {
-    T v[FftCfg<T>::CMAX];
+    T v[NL];
     __device__ __forceinline__ void load(const Tin* __restrict__ x, int64_t in_row, int total, int logP, int col0,
                                          int ncols) {
         const int P1 = (1 << logP) - 1;
 #pragma unroll
-        for (int u = 0; u < FftCfg<T>::CMAX; ++u) {
+        for (int u = 0; u < NL; ++u) {
             const int e = min(u * kFftThreads + (int)threadIdx.x, total - 1);
             const int c = e & P1, j = e >> logP;
             v[u] = (T)x[(int64_t)j * in_row + min(col0 + c, ncols - 1)];
@@ -411,7 +435,7 @@ struct RealTile {
             shr[2 * (((j >> 1) << logP) + c) + (j & 1)] = (T)0;
         }
 #pragma unroll
-        for (int u = 0; u < FftCfg<T>::CMAX; ++u) {
+        for (int u = 0; u < NL; ++u) {
             const int e = u * kFftThreads + (int)threadIdx.x;
             if (e < total) {
                 const int c = e & P1, j = e >> logP;
@@ -444,7 +468,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const Tin* __restrict__ x = static_cast<const Tin*>(in.at(blockIdx.y));
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
     // all input loads in flight before the twiddle copy waits for its own
-    RealTile<T, Tin> tile;
+    RealTile<T, Tin, LoadSlots<T, PL>::value> tile;
     tile.load(x, in_row, Nt << logP, logP, col0, ncols);
     const cx<T>* tw = stage_twiddles<T>(tw_off, twl, N, twg);
     tile.commit(reinterpret_cast<T*>(fft_smem), Nt, N, logP, col0, ncols);
@@ -469,7 +493,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<double>);
     const double* __restrict__ x = in + (int64_t)blockIdx.y * in_batch;
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
-    RealTile<double, double> tile;
+    RealTile<double, double, FftCfg<double>::CMAX> tile;
     tile.load(x, in_row, Nt << logP, logP, col0, ncols);
     const cx<double>* tw = stage_twiddles<double>(tw_off, twl, N, twg);
     tile.commit(reinterpret_cast<double*>(fft_smem), Nt, N, logP, col0, ncols);
@@ -499,7 +523,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 
     // every spectrum load of the tile in flight (one batch: the launcher checks that
     // (N+1) P <= CMAX threads) before the twiddle copy waits for its own
-    constexpr int K = FftCfg<T>::CMAX;
+    constexpr int K = LoadSlots<T, PL>::value;
     const int total = (N + 1) << logP;
     cx<T> val[K];
 #pragma unroll
@@ -581,8 +605,6 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 }
 
 // ----------------------------------------------------------------------------------------
-static constexpr size_t kFftLdsBudget = 64 * 1024;
-
 static size_t elem_of(Real r) { return r == Real::F64 ? 16 : 8; }
 static int cmax_of(Real r) { return r == Real::F64 ? FftCfg<double>::CMAX : FftCfg<float>::CMAX; }
 
@@ -646,6 +668,8 @@ static bool same_plan(const FftPlan& p, CtPlan<Rs...>) {
 
 static int static_plan_id(const FftPlan& p, Real r) {
     if (r != Real::F32 || !twl_of(p.N, r)) return -1;
+    // the kernels size their load slots for the widest tile fft_log_cols allows
+    static_assert(ct_log_cols<float>(420) == 4 && LoadSlots<float, Plan420>::value == 14, "tile rule");
 #define BT_MATCH(ID, PLAN) \
     if (same_plan(p, PLAN{})) return ID;
     BT_STATIC_PLANS(BT_MATCH)

@@ -63,11 +63,11 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
 
 // ---- launchers (sbgemv.hip) ---------------------------------------------------------
 // Per-frequency products with the stored operator Fh[f][s][p] (row stride ldF, frequency
-// stride Nd*ldF).  N: part[b][f][span][s] = sum_{p in span} Fh[f][s][p] mh[b][f][p].
+// stride Nd*ldF).  N: part[b][s][f][span] = sum_{p in span} Fh[f][s][p] mh[b][f][p].
 // C: mo[b][f][p] = sum_s conj(Fh[f][s][p]) dh[b][f][s].
 // Partial sums are laid out part[b][s][f][span] (part_batch = Nd * nfreq * nspan).
 // `var` selects a tuning variant (0 .. sbgemv_variants()-1).
-int sbgemv_n_span(Stor st, int64_t Nm);
+int n_span_cols(Stor st, int64_t Nm, int nfreq);  // columns per span of the N-direction products
 int sbgemv_variants();
 hipError_t launch_sbgemv_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
@@ -79,7 +79,6 @@ hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
 // ---- launchers (sbgemm.hip): k >= 2 right-hand sides on the matrix cores ----------------
 // Same operands and outputs as the single-vector launchers above, for nb right-hand sides in
 // one launch (FP32 or BF16 storage only).  sbgemm_c needs sbgemm_c_lds(nb, Nd) <= 64 KB.
-int sbgemm_n_span(int64_t Nm);
 size_t sbgemm_c_lds(int nb, int Nd);
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,

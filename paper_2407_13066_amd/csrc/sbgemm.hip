@@ -13,7 +13,8 @@
 //   N (for F):  C_f (Nd x 2k) += Fh_f (Nd x 2Nm) B_f (2Nm x 2k), split over column spans
 //               (partial sums part[r][s][f][span], summed in order by the data-side kernel).
 //               A workgroup keeps the whole Nd x 2k accumulator of its span in registers
-//               and streams the right-hand sides through LDS in chunks of 64 columns.
+//               and streams the right-hand sides through LDS in chunks of 256 / 128 / 64 / 32
+//               columns (1 / 2 / 4 / 8 tiles of 8 right-hand sides).
 //   C (for F^T): O_f^T (2k x Nm) = D_f^T (2k x 2Nd) Fh_f (2Nd x Nm): the operator is the
 //               B operand, lanes own output columns p, so each result row of 16 p values
 //               is stored as one contiguous run; no reduction across workgroups.
@@ -37,11 +38,22 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmThreads = 256;
-// complex columns of the vector side staged per LDS chunk (N direction): 64, or 32 for the
-// widest tile so that two chunk buffers stay within 64 KB of LDS
-template <int NT>
+// Complex columns of the vector side staged per LDS chunk (N direction).  On wide launches the
+// narrow tiles take 2 KB of every operator row per chunk (long runs per DRAM page), halved with
+// each doubling of the tile so that two chunk buffers stay within 33 KB of LDS; narrow launches
+// keep 64 columns (17 KB or less, so more workgroups fit a CU).
+template <int NT, bool WIDE>
 struct Chunk {
-    static constexpr int value = NT >= 8 ? 32 : 64;
+    static constexpr int value = NT >= 8 ? 32 : (NT >= 4 || !WIDE ? 64 : (NT >= 2 ? 128 : 256));
+};
+// Launches with fewer (span, frequency) workgroups than this keep 64-column chunks, whose
+// smaller LDS footprint lets more workgroups share a CU.
+constexpr int64_t kWideGrid = 4096;
+// Waves per workgroup of the C kernel: the staged data spectra (NT * 8 rows) are shared by
+// 8 waves once they are large.
+template <int NT>
+struct CWaves {
+    static constexpr int value = NT >= 4 ? 8 : 4;
 };
 
 // Operator loads of the adjoint kernel: streamed once per application, so non-temporal (they
@@ -81,7 +93,7 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // N direction.  Grid (nspan, nfreq); 4 waves; wave w owns row tiles 2w, 2w+1 of each group
 // of 128 rows; NT tiles of 16 real result columns (8 right-hand sides each).
 // LDS: two chunk buffers of nb x kChunk vector entries (row stride kChunk + 2).
-template <bool BF, int NT, int kChunk = Chunk<NT>::value>
+template <bool BF, int NT, int kChunk>
 __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
                                                            int64_t mh_batch, int nb, cx<float>* __restrict__ part,
@@ -233,12 +245,12 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
 }
 
 // =========================================================================================
-// C direction.  Grid (ceil(Nm / 128), nfreq); 4 waves; wave w owns result columns
-// p0 = 128 blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
+// C direction.  Grid (ceil(Nm / (32 W)), nfreq); W waves; wave w owns result columns
+// p0 = 32 W blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
 // result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are
 // staged in LDS once (as the A operand pattern's source).
-template <bool BF, int NT>
-__global__ __launch_bounds__(kGemmThreads) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
+template <bool BF, int NT, int W = CWaves<NT>::value>
+__global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ dh, int64_t dh_batch, int nb,
                                                            cx<float>* __restrict__ mo, int64_t ldv, int64_t mo_batch) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -247,7 +259,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_c(const void* __restric
     const int f = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    for (int e = threadIdx.x; e < NT * 8 * Ndp; e += kGemmThreads) {
+    for (int e = threadIdx.x; e < NT * 8 * Ndp; e += 64 * W) {
         const int r = e / Ndp, s = e % Ndp;
         float re = 0.f, im = 0.f;
         if (r < nb && s < Nd) {
@@ -266,7 +278,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_c(const void* __restric
     }
     __syncthreads();
 
-    const int pbase = blockIdx.x * 128 + wave * 32;
+    const int pbase = blockIdx.x * (32 * W) + wave * 32;
     const int pc[2] = {min(pbase + li, Nm - 1), min(pbase + 16 + li, Nm - 1)};
     const bool tile1 = pbase + 16 < Nm;
     if (pbase >= Nm) return;
@@ -356,13 +368,6 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_c(const void* __restric
 }
 
 // =========================================================================================
-int sbgemm_n_span(int64_t Nm) {
-    // same spans as the single-vector kernel: 4096 columns, or one span rounded to 64 columns
-    const int64_t cs = 4096;
-    const int64_t need = ((Nm + 63) / 64) * 64;
-    return (int)(cs < need ? cs : need);
-}
-
 size_t sbgemm_c_lds(int nb, int Nd) {
     const int NT = nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8));
     return (size_t)NT * 8 * ((Nd + 15) & ~15) * 8;
@@ -374,17 +379,27 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
                            hipStream_t s) {
     if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
-    const int CS = sbgemm_n_span(Nm);
+    const int CS = n_span_cols(st, Nm, nfreq);  // the single-vector kernel's spans (multiples of 256 columns)
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
-    const int ch = NT >= 8 ? Chunk<8>::value : Chunk<1>::value;
+    const bool wide = (int64_t)nspan * nfreq >= kWideGrid;
+    const int ch = wide ? (NT >= 8 ? Chunk<8, true>::value
+                                   : (NT >= 4 ? Chunk<4, true>::value
+                                              : (NT >= 2 ? Chunk<2, true>::value : Chunk<1, true>::value)))
+                        : (NT >= 8 ? Chunk<8, false>::value : Chunk<1, false>::value);
     const size_t lds = (size_t)2 * NT * 8 * (ch + 2) * 8;
     dim3 grid(nspan, nfreq), block(kGemmThreads);
     const cx<float>* m = (const cx<float>*)mh;
     cx<float>* p = (cx<float>*)part;
-#define BT_GN(BFV, NTV) \
-    k_sbgemm_n<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, \
-                                                  part_batch)
+#define BT_GN(BFV, NTV)                                                                                    \
+    do {                                                                                                   \
+        if (wide)                                                                                          \
+            k_sbgemm_n<BFV, NTV, Chunk<NTV, true>::value><<<grid, block, lds, s>>>(                        \
+                Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, part_batch);                   \
+        else                                                                                               \
+            k_sbgemm_n<BFV, NTV, Chunk<NTV, false>::value><<<grid, block, lds, s>>>(                       \
+                Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, part_batch);                   \
+    } while (0)
     const bool bf = st == Stor::BF16;
     switch (NT) {
         case 1: if (bf) BT_GN(true, 1); else BT_GN(false, 1); break;
@@ -402,7 +417,8 @@ hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     const int NT = nt_of(nb);
     const size_t lds = sbgemm_c_lds(nb, Nd);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((Nm + 127) / 128), nfreq), block(kGemmThreads);
+    const int W = NT >= 4 ? CWaves<4>::value : CWaves<1>::value;
+    dim3 grid((unsigned)((Nm + 32 * W - 1) / (32 * W)), nfreq), block(64 * W);
     const cx<float>* d = (const cx<float>*)dh;
     cx<float>* o = (cx<float>*)mo;
 #define BT_GC(BFV, NTV) \

@@ -244,11 +244,14 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
 // ----------------------------------------------------------------------------------------
 static int stor_vec(Stor st) { return st == Stor::C128 ? 2 : (st == Stor::C64 ? 4 : 8); }
 
-int sbgemv_n_span(Stor st, int64_t Nm) {
-    // 4096 columns per span (2048 for FP64), i.e. a 32 KB slice of mh staged in LDS; narrow
-    // operators use one span rounded up to whole 64-lane tiles.
+int n_span_cols(Stor st, int64_t Nm, int nfreq) {
+    // 4096 columns per span (2048 for FP64), i.e. a 32 KB slice of mh staged in LDS, halved
+    // (down to 512) while a launch would have fewer than 2048 (span, frequency) workgroups, so
+    // that small operators still spread over the chip; an operator narrower than one span uses
+    // one span rounded up to whole 64-lane tiles.
     const int tile = kWave * stor_vec(st);
     int64_t cs = (st == Stor::C128) ? 2048 : 4096;
+    while (cs > 512 && ((Nm + cs - 1) / cs) * nfreq < 2048) cs /= 2;
     const int64_t need = ((Nm + tile - 1) / tile) * tile;
     return (int)(cs < need ? cs : need);
 }
@@ -297,7 +300,7 @@ static hipError_t run_c(int var, dim3 grid, hipStream_t s, const void* Fh, int64
 hipError_t launch_sbgemv_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
                            hipStream_t s, int var) {
-    const int CS = sbgemv_n_span(st, Nm);
+    const int CS = n_span_cols(st, Nm, nfreq);
     if (nspan != (Nm + CS - 1) / CS || var < 0 || var >= sbgemv_variants()) return hipErrorInvalidValue;
     dim3 grid(nspan, nfreq, nb);
     switch (st) {
