@@ -360,8 +360,12 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int r = n * 8 + 2 * lg + h;
-                if (r < nb)
-                    mo[(int64_t)r * mo_batch + (int64_t)f * ldv + p] = cx<float>{acc[a][n][2 * h], acc[a][n][2 * h + 1]};
+                if (r < nb) {
+                    // not read again by this launch: non-temporal store
+                    typedef float f2v __attribute__((ext_vector_type(2)));
+                    const f2v w = {acc[a][n][2 * h], acc[a][n][2 * h + 1]};
+                    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(mo + (int64_t)r * mo_batch + (int64_t)f * ldv + p));
+                }
             }
         }
     }

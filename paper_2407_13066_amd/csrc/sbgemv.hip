@@ -232,12 +232,31 @@ __global__ __launch_bounds__(kGemvThreads) void k_sbgemv_c(const S* __restrict__
             consume(s + RB, wb);
         }
     }
+    // The result spectra are not read again by this launch: 16-byte non-temporal stores (a
+    // chunk's CPL values are 16-byte aligned; a chunk that starts before Nm may reach into the
+    // zero padding of the row, which stays inside ldv).
     cx<A>* __restrict__ o = mo + (int64_t)b * mo_batch + (int64_t)f * ldv;
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
         if (!valid[h]) continue;
+        u32x4* dst = reinterpret_cast<u32x4*>(o + tile0 + LN::chunk(lane, h));
+        if constexpr (sizeof(A) == 4) {
 #pragma unroll
-        for (int e = 0; e < CPL; ++e) o[tile0 + LN::chunk(lane, h) + e] = acc[h * CPL + e];
+            for (int q = 0; q < CPL / 2; ++q) {
+                const cx<A> x0 = acc[h * CPL + 2 * q], x1 = acc[h * CPL + 2 * q + 1];
+                const u32x4 w = {__float_as_uint(x0.re), __float_as_uint(x0.im), __float_as_uint(x1.re),
+                                 __float_as_uint(x1.im)};
+                __builtin_nontemporal_store(w, dst + q);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                const cx<A> x = acc[h * CPL + q];
+                const u32x4 w = {(unsigned)__double2loint(x.re), (unsigned)__double2hiint(x.re),
+                                 (unsigned)__double2loint(x.im), (unsigned)__double2hiint(x.im)};
+                __builtin_nontemporal_store(w, dst + q);
+            }
+        }
     }
 }
 
