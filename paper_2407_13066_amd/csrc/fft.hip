@@ -333,6 +333,20 @@ __device__ __forceinline__ void put(bf16c* p, cx<T> v) {
     *p = Store<bf16c>::from(cx<double>{(double)v.re, (double)v.im});
 }
 
+
+// Vector-side outputs are written with non-temporal stores: left as dirty lines in the
+// caches they would be written back while the next kernel streams the operator.
+template <typename T>
+__device__ __forceinline__ void put_nt(cx<float>* p, cx<T> v) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f2v w = {(float)v.re, (float)v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
+}
+template <typename T>
+__device__ __forceinline__ void put_nt(cx<double>* p, cx<T> v) { put(p, v); }
+template <typename T>
+__device__ __forceinline__ void put_nt(bf16c* p, cx<T> v) { put(p, v); }
+
 // Bins f = 0..N of the length-2N real transform from the half-length transform Z held in
 // LDS:  X_f = (Z_f + conj Z_{N-f}) / 2 + W_{2N}^f (Z_f - conj Z_{N-f}) / (2i).
 template <typename T>
@@ -476,7 +490,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     run_fft<T, -1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
-        if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
+        if (col0 + c < ncols) put_nt(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
     }
 }
 
@@ -557,7 +571,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
             const int c = e & P1, j = e >> logP;
             if (e < nout && col0 + c < ncols) {
                 const T v = out_scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
-                x[(int64_t)j * out_row + col0 + c] = a ? fma(add_scale, av[u], v) : v;
+                __builtin_nontemporal_store(a ? fma(add_scale, av[u], v) : v, &x[(int64_t)j * out_row + col0 + c]);
             }
         }
     }
