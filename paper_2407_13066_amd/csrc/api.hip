@@ -222,12 +222,25 @@ Stor vstor(const btoep_op op) { return op->vreal == Real::F64 ? Stor::C128 : Sto
 // side or FP64 storage; the MFMA kernels for nb >= 2 on FP32 / BF16 storage.
 bool use_gemm(const btoep_op op, int nb) { return nb >= 2 && op->stor != Stor::C128 && op->gemm_enabled; }
 
+constexpr int kGemmNGroup = 32;
+
 hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part, int nspan, int64_t part_b,
                   hipStream_t st) {
     const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
-    if (use_gemm(op, nb))
-        return launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b,
-                               st);
+    if (use_gemm(op, nb)) {
+        // groups of at most kGemmNGroup right-hand sides (the 8-tile N kernel is slower than two
+        // 4-tile launches), balanced so that every group keeps >= 2 and runs on the matrix cores
+        const int ng = (nb + kGemmNGroup - 1) / kGemmNGroup;
+        const int g = (nb + ng - 1) / ng;
+        for (int r0 = 0; r0 < nb; r0 += g) {
+            const int n = std::min(g, nb - r0);
+            hipError_t e = launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
+                                           (const char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, n,
+                                           (char*)part + (size_t)r0 * part_b * 8, nspan, part_b, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     return launch_sbgemv_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, vh, op->ldv, vh_b, nb, part, nspan, part_b, st,
                            op->var_n);
 }
