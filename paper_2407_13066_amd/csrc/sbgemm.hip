@@ -44,8 +44,22 @@ constexpr int kGemmThreads = 256;
 // keep 64 columns (17 KB or less, so more workgroups fit a CU).
 template <int NT, bool WIDE>
 struct Chunk {
-    static constexpr int value = NT >= 8 ? 32 : (NT >= 4 || !WIDE ? 64 : (NT >= 2 ? 128 : 256));
+    static constexpr int value = NT >= 2 ? 128 / NT : (WIDE ? 256 : 64);
 };
+// With several tiles the vector side is staged as ready-made B-operand patterns (16 bytes per
+// column instead of 8, see k_sbgemm_n), so the chunk holds 128 / NT columns.
+template <int NT>
+struct Patterns {
+    static constexpr bool value = NT >= 2;
+};
+static constexpr int chunk_of(int NT, bool wide) { return NT >= 2 ? 128 / NT : (wide ? 256 : 64); }
+static_assert(Chunk<1, true>::value == chunk_of(1, true) && Chunk<1, false>::value == chunk_of(1, false) &&
+                  Chunk<2, true>::value == chunk_of(2, true) && Chunk<4, false>::value == chunk_of(4, false) &&
+                  Chunk<8, true>::value == chunk_of(8, true),
+              "host and kernel chunk sizes");
+static size_t sbgemm_n_lds(int NT, int ch) {
+    return NT >= 2 ? (size_t)2 * NT * 8 * (ch + 1) * 16 : (size_t)2 * NT * 8 * (ch + 2) * 8;
+}
 // Launches with fewer (span, frequency) workgroups than this keep 64-column chunks, whose
 // smaller LDS footprint lets more workgroups share a CU.
 constexpr int64_t kWideGrid = 4096;
@@ -92,16 +106,20 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // =========================================================================================
 // N direction.  Grid (nspan, nfreq); 4 waves; wave w owns row tiles 2w, 2w+1 of each group
 // of 128 rows; NT tiles of 16 real result columns (8 right-hand sides each).
-// LDS: two chunk buffers of nb x kChunk vector entries (row stride kChunk + 2).
+// LDS: two chunk buffers of nb x kChunk vector entries.  An entry is the column's value as
+// staged (8 bytes: float complex, or (hi, lo) packed bf16 pairs; row stride kChunk + 2) or,
+// with PAT, both B-operand patterns a lane can need (16 bytes, row stride kChunk + 1): lanes of
+// even result column (real part) take the first 8 bytes, lanes of odd column the second.
 template <bool BF, int NT, int kChunk>
 __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
                                                            int64_t mh_batch, int nb, cx<float>* __restrict__ part,
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
-    constexpr int LDR = kChunk + 2;  // row stride (entries) of a staged chunk
-    // entry = float complex (FP32 path) or (hi, lo) packed bf16 pairs (BF16 path): 8 bytes
+    constexpr bool PAT = Patterns<NT>::value;
+    constexpr int LDR = PAT ? kChunk + 1 : kChunk + 2;  // row stride (entries) of a staged chunk
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    uint2* buf = reinterpret_cast<uint2*>(smem_raw);  // [2][NT*8][LDR]
+    uint2* buf = reinterpret_cast<uint2*>(smem_raw);   // [2][NT*8][LDR] 8-byte entries
+    uint4* buf4 = reinterpret_cast<uint4*>(smem_raw);  // [2][NT*8][LDR] 16-byte entries (PAT)
     const int span = blockIdx.x, f = blockIdx.y;
     const int col0 = span * CS;
     const int ncol = min(CS, Nm - col0);
@@ -121,14 +139,28 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
                 re = v.re;
                 im = v.im;
             }
-            uint2 out;
-            if (BF) {
-                split_bf16(re, im, out.x, out.y);
+            if constexpr (PAT) {
+                // (pairs with Re F, pairs with Im F) for a real-part column, then for an
+                // imaginary-part column: (Re m, -Im m), (Im m, Re m)
+                uint4 out;
+                if (BF) {
+                    uint32_t hi, lo;
+                    split_bf16(re, im, hi, lo);
+                    out = uint4{bf_re_negim(hi), bf_re_negim(lo), bf_im_re(hi), bf_im_re(lo)};
+                } else {
+                    out = uint4{__float_as_uint(re), __float_as_uint(-im), __float_as_uint(im), __float_as_uint(re)};
+                }
+                buf4[(size_t)which * rows_per_buf * LDR + r * LDR + q] = out;
             } else {
-                out.x = __float_as_uint(re);
-                out.y = __float_as_uint(im);
+                uint2 out;
+                if (BF) {
+                    split_bf16(re, im, out.x, out.y);
+                } else {
+                    out.x = __float_as_uint(re);
+                    out.y = __float_as_uint(im);
+                }
+                dst[r * LDR + q] = out;
             }
-            dst[r * LDR + q] = out;
         }
     };
 
@@ -150,6 +182,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
             __syncthreads();
             if (c + 1 < nchunk) stage(c + 1, (c + 1) & 1);
             const uint2* B = buf + (size_t)(c & 1) * rows_per_buf * LDR;
+            const uint4* B4 = buf4 + (size_t)(c & 1) * rows_per_buf * LDR;
             const int cb = col0 + c * kChunk;  // first complex column of the chunk
             if (t0) {
                 // K step = 16 complex columns; lane group lg covers columns 4 lg .. 4 lg + 3
@@ -182,11 +215,18 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
                             const bool imcol = li & 1;
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const uint2 mv = B[r * LDR + q0 + q];
-                                const float mre = __uint_as_float(mv.x), mim = __uint_as_float(mv.y);
                                 // K = (column q, part c): c = 0 real, c = 1 imaginary part of F
-                                const float b0 = imcol ? mim : mre;   // pairs with Re F
-                                const float b1 = imcol ? mre : -mim;  // pairs with Im F
+                                float b0, b1;  // pair with Re F, with Im F
+                                if constexpr (PAT) {
+                                    const uint2 pv = reinterpret_cast<const uint2*>(B4 + r * LDR + q0 + q)[imcol];
+                                    b0 = __uint_as_float(pv.x);
+                                    b1 = __uint_as_float(pv.y);
+                                } else {
+                                    const uint2 mv = B[r * LDR + q0 + q];
+                                    const float mre = __uint_as_float(mv.x), mim = __uint_as_float(mv.y);
+                                    b0 = imcol ? mim : mre;
+                                    b1 = imcol ? mre : -mim;
+                                }
                                 acc[0][n] = mfma_f32(a0[2 * q], b0, acc[0][n]);
                                 acc[0][n] = mfma_f32(a0[2 * q + 1], b1, acc[0][n]);
                                 if (t1) {
@@ -208,9 +248,15 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
                             u32x4 bh, bl;
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const uint2 mv = B[r * LDR + q0 + q];
-                                bh[q] = imcol ? bf_im_re(mv.x) : bf_re_negim(mv.x);
-                                bl[q] = imcol ? bf_im_re(mv.y) : bf_re_negim(mv.y);
+                                if constexpr (PAT) {
+                                    const uint2 pv = reinterpret_cast<const uint2*>(B4 + r * LDR + q0 + q)[imcol];
+                                    bh[q] = pv.x;
+                                    bl[q] = pv.y;
+                                } else {
+                                    const uint2 mv = B[r * LDR + q0 + q];
+                                    bh[q] = imcol ? bf_im_re(mv.x) : bf_re_negim(mv.x);
+                                    bl[q] = imcol ? bf_im_re(mv.y) : bf_re_negim(mv.y);
+                                }
                             }
                             acc[0][n] = mfma_bf16(a0, bh, acc[0][n]);
                             acc[0][n] = mfma_bf16(a0, bl, acc[0][n]);
@@ -387,11 +433,7 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
     const bool wide = (int64_t)nspan * nfreq >= kWideGrid;
-    const int ch = wide ? (NT >= 8 ? Chunk<8, true>::value
-                                   : (NT >= 4 ? Chunk<4, true>::value
-                                              : (NT >= 2 ? Chunk<2, true>::value : Chunk<1, true>::value)))
-                        : (NT >= 8 ? Chunk<8, false>::value : Chunk<1, false>::value);
-    const size_t lds = (size_t)2 * NT * 8 * (ch + 2) * 8;
+    const size_t lds = sbgemm_n_lds(NT, chunk_of(NT, wide));
     dim3 grid(nspan, nfreq), block(kGemmThreads);
     const cx<float>* m = (const cx<float>*)mh;
     cx<float>* p = (cx<float>*)part;
