@@ -222,15 +222,13 @@ Stor vstor(const btoep_op op) { return op->vreal == Real::F64 ? Stor::C128 : Sto
 // side or FP64 storage; the MFMA kernels for nb >= 2 on FP32 / BF16 storage.
 bool use_gemm(const btoep_op op, int nb) { return nb >= 2 && op->stor != Stor::C128 && op->gemm_enabled; }
 
-constexpr int kGemmNGroup = 32;
-
 hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part, int nspan, int64_t part_b,
                   hipStream_t st) {
     const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
     if (use_gemm(op, nb)) {
-        // groups of at most kGemmNGroup right-hand sides (the 8-tile N kernel is slower than two
-        // 4-tile launches), balanced so that every group keeps >= 2 and runs on the matrix cores
-        const int ng = (nb + kGemmNGroup - 1) / kGemmNGroup;
+        // groups of at most kGemmNMax right-hand sides, balanced so that every group keeps >= 2
+        // and runs on the matrix cores
+        const int ng = (nb + kGemmNMax - 1) / kGemmNMax;
         const int g = (nb + ng - 1) / ng;
         for (int r0 = 0; r0 < nb; r0 += g) {
             const int n = std::min(g, nb - r0);

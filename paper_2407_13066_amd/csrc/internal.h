@@ -80,6 +80,9 @@ hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
 // Same operands and outputs as the single-vector launchers above, for nb right-hand sides in
 // one launch (FP32 or BF16 storage only).  sbgemm_c needs sbgemm_c_lds(nb, Nd) <= 64 KB.
 size_t sbgemm_c_lds(int nb, int Nd);
+// The N launcher takes at most kGemmNMax right-hand sides (an 8-tile N kernel measured slower
+// than two 4-tile launches); callers group larger batches.
+constexpr int kGemmNMax = 32;
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
                            int nspan, int64_t part_batch, hipStream_t s);

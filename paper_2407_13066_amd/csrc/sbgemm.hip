@@ -13,8 +13,9 @@
 //   N (for F):  C_f (Nd x 2k) += Fh_f (Nd x 2Nm) B_f (2Nm x 2k), split over column spans
 //               (partial sums part[r][s][f][span], summed in order by the data-side kernel).
 //               A workgroup keeps the whole Nd x 2k accumulator of its span in registers
-//               and streams the right-hand sides through LDS in chunks of 256 / 128 / 64 / 32
-//               columns (1 / 2 / 4 / 8 tiles of 8 right-hand sides).
+//               and streams the right-hand sides through LDS in chunks (256 or 64 columns
+//               for one tile of 8 right-hand sides; 128 / NT columns of ready-made operand
+//               patterns for NT = 2 or 4 tiles).  At most 32 right-hand sides per launch.
 //   C (for F^T): O_f^T (2k x Nm) = D_f^T (2k x 2Nd) Fh_f (2Nd x Nm): the operator is the
 //               B operand, lanes own output columns p, so each result row of 16 p values
 //               is stored as one contiguous run; no reduction across workgroups.
@@ -428,7 +429,7 @@ static int nt_of(int nb) { return nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
                            hipStream_t s) {
-    if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+    if (st == Stor::C128 || nb < 1 || nb > kGemmNMax) return hipErrorInvalidValue;
     const int CS = n_span_cols(st, Nm, nfreq);  // the single-vector kernel's spans (multiples of 256 columns)
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
@@ -450,8 +451,7 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     switch (NT) {
         case 1: if (bf) BT_GN(true, 1); else BT_GN(false, 1); break;
         case 2: if (bf) BT_GN(true, 2); else BT_GN(false, 2); break;
-        case 4: if (bf) BT_GN(true, 4); else BT_GN(false, 4); break;
-        default: if (bf) BT_GN(true, 8); else BT_GN(false, 8); break;
+        default: if (bf) BT_GN(true, 4); else BT_GN(false, 4); break;
     }
 #undef BT_GN
     return hipGetLastError();
