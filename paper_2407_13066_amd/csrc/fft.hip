@@ -148,6 +148,100 @@ struct Dft<5, DIR, T> : DftOdd<5, DIR, T> {};
 template <int DIR, typename T>
 struct Dft<7, DIR, T> : DftOdd<7, DIR, T> {};
 
+// cos / sin of 2 pi m / N (m < N) for the twiddles inside the composite radices.
+template <int N>
+struct RootTable;
+template <>
+struct RootTable<16> {
+    __device__ static double c(int m) {
+        constexpr double t[16] = {1, 0.92387953251128674, 0.70710678118654757, 0.38268343236508984, 0, -0.38268343236508973,
+                                   -0.70710678118654746, -0.92387953251128674, -1, -0.92387953251128685, -0.70710678118654768,
+                                   -0.38268343236509034, 0, 0.38268343236509, 0.70710678118654735, 0.92387953251128652};
+        return t[m];
+    }
+    __device__ static double s(int m) {
+        constexpr double t[16] = {0, 0.38268343236508978, 0.70710678118654746, 0.92387953251128674, 1, 0.92387953251128674,
+                                   0.70710678118654757, 0.38268343236508989, 0, -0.38268343236508967, -0.70710678118654746,
+                                   -0.92387953251128652, -1, -0.92387953251128663, -0.70710678118654768, -0.38268343236509039};
+        return t[m];
+    }
+};
+template <>
+struct RootTable<20> {
+    __device__ static double c(int m) {
+        constexpr double t[20] = {1, 0.95105651629515353, 0.80901699437494745, 0.58778525229247314, 0.30901699437494745, 0,
+                                   -0.30901699437494734, -0.58778525229247303, -0.80901699437494734, -0.95105651629515353, -1,
+                                   -0.95105651629515375, -0.80901699437494756, -0.58778525229247325, -0.30901699437494756, 0,
+                                   0.30901699437494723, 0.58778525229247292, 0.80901699437494734, 0.95105651629515353};
+        return t[m];
+    }
+    __device__ static double s(int m) {
+        constexpr double t[20] = {0, 0.3090169943749474, 0.58778525229247314, 0.80901699437494745, 0.95105651629515353, 1,
+                                   0.95105651629515364, 0.80901699437494745, 0.58778525229247325, 0.30901699437494751, 0,
+                                   -0.3090169943749469, -0.58778525229247303, -0.80901699437494734, -0.95105651629515353, -1,
+                                   -0.95105651629515364, -0.80901699437494756, -0.58778525229247336, -0.30901699437494762};
+        return t[m];
+    }
+};
+template <>
+struct RootTable<21> {
+    __device__ static double c(int m) {
+        constexpr double t[21] = {1, 0.95557280578614068, 0.82623877431599491, 0.62348980185873359, 0.36534102436639498,
+                                   0.074730093586424393, -0.22252093395631434, -0.49999999999999978, -0.73305187182982634,
+                                   -0.90096886790241903, -0.98883082622512852, -0.98883082622512863, -0.90096886790241915,
+                                   -0.73305187182982623, -0.50000000000000044, -0.22252093395631459, 0.074730093586424365,
+                                   0.36534102436639537, 0.62348980185873337, 0.82623877431599446, 0.95557280578614057};
+        return t[m];
+    }
+    __device__ static double s(int m) {
+        constexpr double t[21] = {0, 0.29475517441090421, 0.56332005806362206, 0.7818314824680298, 0.93087374864420425,
+                                   0.99720379718118013, 0.97492791218182362, 0.86602540378443871, 0.68017273777091936,
+                                   0.43388373911755823, 0.14904226617617472, -0.14904226617617403, -0.43388373911755801,
+                                   -0.68017273777091947, -0.86602540378443837, -0.97492791218182362, -0.99720379718118013,
+                                   -0.93087374864420414, -0.78183148246802991, -0.56332005806362273, -0.29475517441090471};
+        return t[m];
+    }
+};
+
+// Composite radix N = N1 N2 in registers (Cooley-Tukey): with n = N2 n1 + n2 and
+// k = k1 + N1 k2,  X[k] = sum_{n2} W_N^{n2 k1} W_{N2}^{n2 k2} sum_{n1} x[n] W_{N1}^{n1 k1},
+// W_M = exp(DIR 2 pi i / M): N2 DFTs of size N1, the twiddles, then N1 DFTs of size N2.
+template <int N1, int N2, int DIR, typename T>
+struct DftComp {
+    __device__ static void run(cx<T>* v) {
+        constexpr int N = N1 * N2;
+        cx<T> y[N2][N1];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) y[n2][n1] = v[N2 * n1 + n2];
+            Dft<N1, DIR, T>::run(y[n2]);
+#pragma unroll
+            for (int k1 = 1; k1 < N1; ++k1) {
+                if (n2 == 0) continue;
+                const int m = n2 * k1;  // < N
+                const cx<T> w = cx<T>{(T)RootTable<N>::c(m), (T)(DIR * RootTable<N>::s(m))};
+                y[n2][k1] = cmul(y[n2][k1], w);
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+            cx<T> b[N2];
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) b[n2] = y[n2][k1];
+            Dft<N2, DIR, T>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) v[k1 + N1 * k2] = b[k2];
+        }
+    }
+};
+template <int DIR, typename T>
+struct Dft<16, DIR, T> : DftComp<4, 4, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<20, DIR, T> : DftComp<4, 5, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<21, DIR, T> : DftComp<3, 7, DIR, T> {};
+
 // ----------------------------------------------------------------------------------------
 // One Stockham pass of radix R over all P columns held in LDS.  Ns = product of the radices
 // already applied.  Butterfly j (< N/R) of column c reads elements j + r N/R, multiplies by
@@ -656,12 +750,15 @@ static int pick_log_cols(int N, Real r, int ncols, int nb) {
     return lp;
 }
 
-// Index of the compile-time plan equal to `plan` (FP32 kernels with LDS twiddles), or -1.
+// Vector-side transforms (many columns per workgroup) use two-pass plans where a composite
+// radix (16 = 4 x 4, 20 = 4 x 5, 21 = 3 x 7) fits in registers: every pass costs a trip through
+// LDS and a workgroup barrier.  The data-side kernel transforms one column per workgroup and
+// keeps the finer plans, which give more threads work per pass.
 typedef CtPlan<8, 4> Plan32;
 typedef CtPlan<8, 8> Plan64;
-typedef CtPlan<8, 8, 2> Plan128;
-typedef CtPlan<8, 8, 4> Plan256;
-typedef CtPlan<4, 5, 3, 7> Plan420;
+typedef CtPlan<8, 16> Plan128;
+typedef CtPlan<16, 16> Plan256;
+typedef CtPlan<20, 21> Plan420;
 typedef CtPlan<8, 8, 8> Plan512;
 #define BT_STATIC_PLANS(X) \
     X(0, Plan32)           \
@@ -670,22 +767,27 @@ typedef CtPlan<8, 8, 8> Plan512;
     X(3, Plan256)          \
     X(4, Plan420)          \
     X(5, Plan512)
+typedef CtPlan<8, 8, 2> Plan128f;
+typedef CtPlan<8, 8, 4> Plan256f;
+typedef CtPlan<4, 5, 3, 7> Plan420f;
+#define BT_STATIC_PLANS_FINE(X) \
+    X(0, Plan32)                \
+    X(1, Plan64)                \
+    X(2, Plan128f)              \
+    X(3, Plan256f)              \
+    X(4, Plan420f)              \
+    X(5, Plan512)
 
-template <int... Rs>
-static bool same_plan(const FftPlan& p, CtPlan<Rs...>) {
-    const int rs[] = {Rs...};
-    if (p.npass != (int)sizeof...(Rs)) return false;
-    for (int i = 0; i < p.npass; ++i)
-        if (p.radix[i] != rs[i]) return false;
-    return true;
-}
-
+// Index of the compile-time plan of `plan`'s length (FP32 kernels with LDS twiddles), or -1;
+// the same index selects the plan of that length in either table.
 static int static_plan_id(const FftPlan& p, Real r) {
     if (r != Real::F32 || !twl_of(p.N, r)) return -1;
     // the kernels size their load slots for the widest tile fft_log_cols allows
     static_assert(ct_log_cols<float>(420) == 4 && LoadSlots<float, Plan420>::value == 14, "tile rule");
+    // a compile-time plan applies to any transform of its length (its own radices replace
+    // the runtime factorisation; the twiddle table depends on N only)
 #define BT_MATCH(ID, PLAN) \
-    if (same_plan(p, PLAN{})) return ID;
+    if (p.N == PLAN::N) return ID;
     BT_STATIC_PLANS(BT_MATCH)
 #undef BT_MATCH
     return -1;
@@ -801,7 +903,7 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
         else                    \
             BT_DS(true, PLAN);  \
         break;
-            BT_STATIC_PLANS(BT_CASE)
+            BT_STATIC_PLANS_FINE(BT_CASE)
 #undef BT_CASE
             default:
                 if (dout)
