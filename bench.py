@@ -278,6 +278,51 @@ def graph_launch_benchmark(bt, ops, ex_graph, ex_eager, reps=200):
     return out
 
 
+def paper_shapes_benchmark(bt):
+    """The paper's single-GPU shapes in FP64 (its precision), as context: Nt=2000, Nd=7,
+    Nm=60000 (its step breakdown), Nt=2000, Nd=100, Nm=4000 (largest of its Nm x Nd sweep) and
+    Nm=800, Nd=100, Nt in {1000, 10000} (ends of its Nt sweep; Nt = 10000 needs four-step
+    transforms).  F and F^T times after autotuning (which also picks the transform mode), and
+    the effective bandwidth of F: operator + m + spectra written and read + d, per F time."""
+    import torch
+    import synth
+    out = []
+    for Nt, Nd, Nm in ((2000, 7, 60000), (2000, 100, 4000), (1000, 100, 800), (10000, 100, 800)):
+        blocks = synth.blocks(Nt, Nd, Nm, Nt / 7.0, stream=20)
+        op = bt.btoep_create(blocks, "f64")
+        del blocks
+        tune = bt.btoep_autotune(op, reps=3)
+        m = torch.randn((Nt, Nm), dtype=torch.float64, device="cuda")
+        d = torch.randn((Nt, Nd), dtype=torch.float64, device="cuda")
+
+        def per_call(fn, reps=10):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3 / reps
+
+        f_ms = per_call(lambda: bt.btoep_apply_F(op, m))
+        ft_ms = per_call(lambda: bt.btoep_apply_FT(op, d))
+        nf = op.info["nfreq"]
+        f_bytes = op.info["fhat_bytes"] + 8 * Nt * Nm + 2 * 16 * nf * Nm + 8 * Nt * Nd
+        gbs = f_bytes / (f_ms * 1e-3) / 1e9
+        res = {"Nt": Nt, "Nd": Nd, "Nm": Nm, "storage": "c128", "fhat_GB": round(op.info["fhat_bytes"] / 1e9, 2),
+               "F_ms": round(f_ms, 3), "FT_ms": round(ft_ms, 3), "F_GBs": round(gbs, 1),
+               "F_pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 1),
+               "transforms": "four-step" if tune["fft_four_step"] else "single-pass",
+               "transform_pair_ms": tune["ms_fft"]}
+        log("paper shape Nt=%d Nd=%d Nm=%d FP64: F %.3f ms (%.0f GB/s), F^T %.3f ms, %s transforms" % (
+            Nt, Nd, Nm, f_ms, gbs, ft_ms, res["transforms"]))
+        out.append(res)
+        op.destroy()
+        del m, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def cg_benchmark(bt):
     """Inverse-problem CG: H = sigma^-2 F^T F + alpha I with sigma = 1e-2, alpha = 1e-3 on
     Nt=256, Nd=64, Nm=16384 (blocks N(0,1) exp(-k/(Nt/7))), d = F m_true + N(0, sigma^2),
@@ -344,6 +389,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=150,
                     help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solve measurement")
+    ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape (FP64) context runs")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
                     help="parameter columns of the operator the CPU oracle is timed on")
     args = ap.parse_args()
@@ -394,11 +440,13 @@ def main():
     Hm = torch.empty_like(m)
     d = torch.empty((Nt, Nd), dtype=torch.float32, device=dev)
     mt = torch.empty_like(m)
-    ws = torch.empty(bt.btoep_workspace_size(op, "H", 1), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
     tune = bt.btoep_autotune(op, reps=5, stream=stream)
-    log("autotune: N %s -> %d, C %s -> %d" % (tune["ms_n"], tune["var_n"], tune["ms_c"], tune["var_c"]))
+    log("autotune: N %s -> %d, C %s -> %d; transforms %s ms (single-pass, four-step) -> %s" % (
+        tune["ms_n"], tune["var_n"], tune["ms_c"], tune["var_c"], tune["ms_fft"],
+        "four-step" if tune["fft_four_step"] else "single-pass"))
+    ws = torch.empty(bt.btoep_workspace_size(op, "H", 1), dtype=torch.uint8, device=dev)  # after the mode choice
 
     def step():
         bt.btoep_apply_H(op, m, noise_prec, prior_prec, out=Hm, ws=ws, stream=stream)
@@ -526,6 +574,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cg:
         result["cg"] = cg_benchmark(bt)
+        torch.cuda.empty_cache()
+    if not args.no_paper_shapes:
+        result["paper_shapes"] = paper_shapes_benchmark(bt)
         torch.cuda.empty_cache()
     if args.serving_requests > 0:
         result["serving"] = serving_benchmark(bt, args.serving_requests, rates=(0.5, 0.9))

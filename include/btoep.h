@@ -193,18 +193,34 @@ btoep_status btoep_cg_solve(btoep_op op_lo, btoep_op op_hi, int64_t k, double no
 /*
  * Autotuning: times every variant of the single-right-hand-side product kernels (row block
  * size, non-temporal or cached operator loads) on this operator, `reps` launches each on
- * `stream`, and keeps the fastest for later applies.  Uses the operator's own workspace
- * (allocated if needed) and writes nothing the caller owns.  Times are milliseconds per
- * launch; entries past `nvar` are unused.
+ * `stream`, and keeps the fastest for later applies; when both transform modes apply (see
+ * btoep_set_fft), times the vector-side transform pair in each and keeps the faster.  Uses
+ * the operator's own workspace and scratch it allocates (synchronises the device) and writes
+ * nothing the caller owns.  Times are milliseconds per launch; entries past `nvar` are unused.
  */
 typedef struct {
     int nvar;
     int var_n, var_c;    /* chosen variants */
     double ms_n[8];      /* product for F   */
     double ms_c[8];      /* product for F^T */
+    int fft_four_step;   /* transform mode kept: 1 four-step, 0 single-pass               */
+    double ms_fft[2];    /* forward + inverse vector-side transforms of one right-hand
+                            side, single-pass and four-step (0 when a mode does not apply) */
 } btoep_tune_result;
 
 btoep_status btoep_autotune(btoep_op op, int reps, void* stream, btoep_tune_result* out);
+
+/*
+ * Transform mode (paper section 2.4: one length-2N DFT per time series; only the order of the
+ * arithmetic changes).  n1 = 0: automatic (single-pass transforms in one workgroup's LDS when
+ * a length-N series fits, else four-step transforms N = N1 N2 with N1 near sqrt(N)); n1 > 1:
+ * four-step transforms with first factor n1 (must divide N); n1 < 0: single-pass (when it
+ * fits).  Synchronises the device; workspace sizes change with the mode (query them again).
+ * BTOEP_ERR_INVALID_ARG for an n1 that does not divide N or gives factors without a column
+ * tile, BTOEP_ERR_UNSUPPORTED for single-pass on a series that does not fit; the operator then
+ * keeps the automatic mode.
+ */
+btoep_status btoep_set_fft(btoep_op op, int64_t n1);
 
 /* Pins the variants (0 .. nvar-1) and whether k >= 2 right-hand sides use the matrix-core
  * kernels (use_mfma != 0, the default) or one single-vector product per right-hand side. */

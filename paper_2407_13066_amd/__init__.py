@@ -57,7 +57,8 @@ class KernelTime(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("nvar", ctypes.c_int), ("var_n", ctypes.c_int), ("var_c", ctypes.c_int),
-                ("ms_n", ctypes.c_double * 8), ("ms_c", ctypes.c_double * 8)]
+                ("ms_n", ctypes.c_double * 8), ("ms_c", ctypes.c_double * 8), ("fft_four_step", ctypes.c_int),
+                ("ms_fft", ctypes.c_double * 2)]
 
 
 def load_library(path=LIB_PATH):
@@ -87,6 +88,7 @@ def load_library(path=LIB_PATH):
                             sz, vp], st),
         "btoep_autotune": ([vp, ctypes.c_int, vp, ctypes.POINTER(TuneResult)], st),
         "btoep_set_tuning": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
+        "btoep_set_fft": ([vp, i64], st),
         "btoep_profile_enable": ([vp, ctypes.c_int], st),
         "btoep_profile_read": ([vp, ctypes.POINTER(KernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], st),
         "btoep_cg_start": ([vp, i64, dbl, dbl, vp, vp, dbl, vp, ctypes.POINTER(vp)], st),
@@ -331,15 +333,23 @@ def btoep_profile_read(op):
 
 
 def btoep_autotune(op, reps=5, stream=None):
-    """Time the single-vector product variants on this operator and keep the fastest.
+    """Time the single-vector product variants (and, where both apply, the two transform
+    modes) on this operator and keep the fastest.
 
-    Returns {"var_n", "var_c", "ms_n": [...], "ms_c": [...]} (milliseconds per launch).
+    Returns {"var_n", "var_c", "ms_n": [...], "ms_c": [...], "fft_four_step", "ms_fft": [single,
+    four-step]} (milliseconds per launch).
     """
     r = TuneResult()
     _check(load_library().btoep_autotune(op.handle, int(reps), _stream(stream), ctypes.byref(r)),
            "btoep_autotune", op.handle)
     return {"var_n": r.var_n, "var_c": r.var_c, "ms_n": [round(r.ms_n[i], 4) for i in range(r.nvar)],
-            "ms_c": [round(r.ms_c[i], 4) for i in range(r.nvar)]}
+            "ms_c": [round(r.ms_c[i], 4) for i in range(r.nvar)], "fft_four_step": bool(r.fft_four_step),
+            "ms_fft": [round(r.ms_fft[0], 4), round(r.ms_fft[1], 4)]}
+
+
+def btoep_set_fft(op, n1=0):
+    """Transform mode: 0 automatic, n1 > 1 four-step with first factor n1, n1 < 0 single-pass."""
+    _check(load_library().btoep_set_fft(op.handle, int(n1)), "btoep_set_fft", op.handle)
 
 
 def btoep_set_tuning(op, var_n, var_c, use_mfma=True):

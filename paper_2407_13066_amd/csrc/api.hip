@@ -28,6 +28,13 @@ struct btoep_op_s {
     FftPlan plan{};
     void* tw64 = nullptr;  // exp(-2 pi i t / L), t < L, complex FP64
     void* tw32 = nullptr;  // same, complex FP32
+    // four-step transforms (long series): N = lp1.N * lp2.N, sub-twiddle tables per type
+    bool fft_long = false;
+    FftPlan lp1{}, lp2{};
+    void* ltw1_64 = nullptr;
+    void* ltw2_64 = nullptr;
+    void* ltw1_32 = nullptr;
+    void* ltw2_32 = nullptr;
     bool gemm_enabled = true;  // MFMA kernels for several right-hand sides
     int var_n = 3, var_c = 3;  // single-vector kernel variants (see sbgemv_variants)
     void* ws = nullptr;    // operator-owned workspace (used when the caller passes none)
@@ -113,9 +120,60 @@ int64_t nspan_of(const btoep_op op) {
     return (op->Nm + cs - 1) / cs;
 }
 
-// Workspace layout of one apply over nb right-hand sides.
+// exp(-2 pi i t / (2 n)), t < 2n, in FP64 and FP32, uploaded to new device arrays.
+hipError_t upload_twiddles(int64_t n, void*& t64, void*& t32) {
+    std::vector<double> a(4 * n);
+    std::vector<float> b(4 * n);
+    for (int64_t t = 0; t < 2 * n; ++t) {
+        const double ang = -M_PI * (double)t / (double)n;
+        a[2 * t] = std::cos(ang);
+        a[2 * t + 1] = std::sin(ang);
+        b[2 * t] = (float)a[2 * t];
+        b[2 * t + 1] = (float)a[2 * t + 1];
+    }
+    hipError_t e = hipMalloc(&t64, a.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&t32, b.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(t64, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t32, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice);
+    return e;
+}
+
+// Four-step split N = N1 N2: N1 = n1 when given (must divide N), else the divisor nearest
+// sqrt(N) from below for which both passes fit a column tile in FP64.
+bool long_split(int64_t N, int64_t n1, FftPlan& p1, FftPlan& p2) {
+    auto ok = [&](int64_t a) {
+        return a > 1 && N % a == 0 && N / a > 1 && N / a <= 65535 && long_log_cols((int)a, (int)(N / a), Real::F64) >= 0 &&
+               make_plan(a, p1) && make_plan(N / a, p2);
+    };
+    if (n1 > 0) return ok(n1);
+    for (int64_t a = (int64_t)std::sqrt((double)N); a > 1; --a)
+        if (ok(a)) return true;
+    return false;
+}
+
+// Switch an operator to four-step transforms with first factor n1 (0: automatic), or back to
+// single-pass transforms (n1 < 0).
+btoep_status set_long(btoep_op op, int64_t n1) {
+    for (void** q : {&op->ltw1_64, &op->ltw2_64, &op->ltw1_32, &op->ltw2_32}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    op->fft_long = false;
+    if (n1 < 0) return fft_log_cols((int)op->N, Real::F64) >= 0 ? BTOEP_OK : BTOEP_ERR_UNSUPPORTED;
+    FftPlan p1, p2;
+    if (!long_split(op->N, n1, p1, p2)) return n1 > 0 ? BTOEP_ERR_INVALID_ARG : BTOEP_ERR_UNSUPPORTED;
+    BT_HIP(op, upload_twiddles(p1.N, op->ltw1_64, op->ltw1_32));
+    BT_HIP(op, upload_twiddles(p2.N, op->ltw2_64, op->ltw2_32));
+    op->lp1 = p1;
+    op->lp2 = p2;
+    op->fft_long = true;
+    return BTOEP_OK;
+}
+
+// Workspace layout of one apply over nb right-hand sides (four-step transforms add a complex
+// scratch of N rows, the data spectra summed over spans and, for H, the truncated data).
 struct ApplyWs {
-    size_t vh = 0, part = 0, dh = 0, total = 0;
+    size_t vh = 0, part = 0, dh = 0, tmp = 0, spec = 0, dtmp = 0, total = 0;
 };
 ApplyWs apply_layout(const btoep_op op, btoep_which which, int64_t nb) {
     const size_t c = 2 * vbytes(op);
@@ -133,6 +191,14 @@ ApplyWs apply_layout(const btoep_op op, btoep_which which, int64_t nb) {
     if (which == BTOEP_APPLY_FT || which == BTOEP_APPLY_H) {
         w.dh = off;
         off += dh;
+    }
+    if (op->fft_long) {
+        w.tmp = off;
+        off += align_up((size_t)nb * op->N * std::max<int64_t>(op->ldv, op->Nd) * c, 256);
+        w.spec = off;
+        off += align_up((size_t)nb * op->nfreq * op->Nd * c, 256);
+        w.dtmp = off;
+        off += align_up((size_t)nb * op->Nt * op->Nd * vbytes(op), 256);
     }
     w.total = off;
     return w;
@@ -265,57 +331,107 @@ hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, i
     return launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, dh, dh_b, nb, vh, op->ldv, vh_b, st, op->var_c);
 }
 
-// One pipeline launch sequence over nb <= kMaxBatch right-hand sides.
+// Vector-side transforms of nb right-hand sides: m [k][Nt][Nm] (row Nm) -> spectra
+// vh[k][f][ldv], and back with out = inv_n x + add_scale * add; single-pass or four-step
+// through tmp (N x ldv per right-hand side) by the operator's mode.
+hipError_t vec_r2c(btoep_op op, int nb, const PtrBatch& in, void* vh, void* tmp, hipStream_t st) {
+    const int64_t ldv = op->ldv, vh_b = op->nfreq * op->ldv;
+    const Real vr = op->vreal;
+    if (op->fft_long)
+        return launch_long_r2c(vr, vr, vstor(op), in, 0, op->Nm, nb, (int)op->Nt, (int)op->Nm, tmp, ldv,
+                               op->N * ldv, vh, ldv, vh_b, op->lp1, op->lp2,
+                               vr == Real::F64 ? op->ltw1_64 : op->ltw1_32,
+                               vr == Real::F64 ? op->ltw2_64 : op->ltw2_32, tw_of(op), st);
+    return launch_fft_r2c(vr, vr, vstor(op), in, op->Nm, nb, vh, ldv, vh_b, (int)op->Nt, (int)op->Nm, op->plan,
+                          tw_of(op), st);
+}
+hipError_t vec_c2r(btoep_op op, int nb, const void* vh, void* tmp, const PtrBatch& out, const PtrBatch& add,
+                   double add_scale, hipStream_t st) {
+    const int64_t ldv = op->ldv, vh_b = op->nfreq * op->ldv;
+    const double inv_n = 1.0 / (double)op->N;
+    const Real vr = op->vreal;
+    if (op->fft_long)
+        return launch_long_c2r(vr, vh, ldv, vh_b, nb, tmp, ldv, op->N * ldv, out, op->Nm, add, add_scale,
+                               (int)op->Nt, (int)op->Nm, op->lp1, op->lp2, vr == Real::F64 ? op->ltw1_64 : op->ltw1_32,
+                               vr == Real::F64 ? op->ltw2_64 : op->ltw2_32, tw_of(op), inv_n, st);
+    return launch_fft_c2r(vr, vh, ldv, vh_b, nb, out, op->Nm, add, add_scale, (int)op->Nt, (int)op->Nm, op->plan,
+                          tw_of(op), inv_n, st);
+}
+
+// One pipeline launch sequence over nb <= kMaxBatch right-hand sides.  Each transform step
+// runs single-pass or, for operators switched to four-step transforms, as two passes through
+// the scratch array of the workspace.
 btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& in, const PtrBatch& out,
                        double noise_prec, double prior_prec, char* ws, hipStream_t st) {
     const ApplyWs w = apply_layout(op, which, nb);
     void* vh = ws + w.vh;
     void* part = ws + w.part;
     void* dh = ws + w.dh;
+    void* tmp = ws + w.tmp;
+    void* spec = ws + w.spec;
+    char* dtmp = ws + w.dtmp;
     const int Nt = (int)op->Nt, Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
     const int nspan = (int)nspan_of(op);
     const int64_t vh_b = op->nfreq * op->ldv, part_b = op->nfreq * nspan * op->Nd, dh_b = op->nfreq * op->Nd;
+    const int64_t N = op->N, ldv = op->ldv;
     const double inv_n = 1.0 / (double)op->N;
     const void* tw = tw_of(op);
+    const bool lg = op->fft_long;
+    const void* tw1 = op->vreal == Real::F64 ? op->ltw1_64 : op->ltw1_32;
+    const void* tw2 = op->vreal == Real::F64 ? op->ltw2_64 : op->ltw2_32;
+    const Real vr = op->vreal;
     PtrBatch none{};
+
+    // m side: [k][Nt][Nm] -> spectra vh[k][f][ldv], and back (with the prior term for H)
+    auto r2c_m = [&]() { return vec_r2c(op, nb, in, vh, tmp, st); };
+    auto c2r_m = [&](const PtrBatch& add, double add_scale) {
+        return vec_c2r(op, nb, vh, tmp, out, add, add_scale, st);
+    };
+    // d side: [k][Nt][Nd] -> data spectra dh[k][f][Nd]
+    auto r2c_d = [&](const PtrBatch& din) {
+        return lg ? launch_long_r2c(vr, vr, vstor(op), din, 0, Nd, nb, Nt, Nd, tmp, Nd, N * Nd, dh, Nd, dh_b,
+                                    op->lp1, op->lp2, tw1, tw2, tw, st)
+                  : launch_fft_r2c(vr, vr, vstor(op), din, Nd, nb, dh, Nd, dh_b, Nt, Nd, op->plan, tw, st);
+    };
+    // partial sums -> d (F) or -> truncated, scaled and transformed again (H)
+    auto dside = [&](bool hmode, double scale) -> hipError_t {
+        if (!lg)
+            return hmode ? launch_dside(vr, part, nspan, part_b, nb, nullptr, dh, dh_b, Nt, Nd, op->plan, tw, scale, st)
+                         : launch_dside(vr, part, nspan, part_b, nb, &out, nullptr, 0, Nt, Nd, op->plan, tw, scale, st);
+        hipError_t e = launch_sum_spans(vr, part, nspan, part_b, spec, (int64_t)nf * Nd, nf, Nd, nb, st);
+        if (e != hipSuccess) return e;
+        if (!hmode)
+            return launch_long_c2r(vr, spec, Nd, (int64_t)nf * Nd, nb, tmp, Nd, N * Nd, out, Nd, none, 0.0, Nt, Nd,
+                                   op->lp1, op->lp2, tw1, tw2, tw, scale, st);
+        PtrBatch dt{};
+        for (int b = 0; b < nb; ++b) dt.p[b] = dtmp + (size_t)b * Nt * Nd * vbytes(op);
+        e = launch_long_c2r(vr, spec, Nd, (int64_t)nf * Nd, nb, tmp, Nd, N * Nd, dt, Nd, none, 0.0, Nt, Nd, op->lp1,
+                            op->lp2, tw1, tw2, tw, scale, st);
+        return e == hipSuccess ? r2c_d(dt) : e;
+    };
+
     if (which == BTOEP_APPLY_F || which == BTOEP_APPLY_H) {
-        BT_HIP(op, timed(op, K_R2C_M, st, [&] {
-            return launch_fft_r2c(op->vreal, op->vreal, vstor(op), in, Nm, nb, vh, op->ldv, vh_b, Nt, Nm, op->plan, tw,
-                                  st);
-        }));
+        BT_HIP(op, timed(op, K_R2C_M, st, r2c_m));
         BT_HIP(op, timed(op, K_SBGEMV_N, st, [&] {
             return prod_n(op, nb, vh, vh_b, part, nspan, part_b, st);
         }));
         if (which == BTOEP_APPLY_F) {
-            BT_HIP(op, timed(op, K_DSIDE_F, st, [&] {
-                return launch_dside(op->vreal, part, nspan, part_b, nb, &out, nullptr, 0, Nt, Nd, op->plan, tw, inv_n,
-                                    st);
-            }));
+            BT_HIP(op, timed(op, K_DSIDE_F, st, [&] { return dside(false, inv_n); }));
             return BTOEP_OK;
         }
-        BT_HIP(op, timed(op, K_DSIDE_H, st, [&] {
-            return launch_dside(op->vreal, part, nspan, part_b, nb, nullptr, dh, dh_b, Nt, Nd, op->plan, tw,
-                                noise_prec * inv_n, st);
-        }));
+        BT_HIP(op, timed(op, K_DSIDE_H, st, [&] { return dside(true, noise_prec * inv_n); }));
         BT_HIP(op, timed(op, K_SBGEMV_C, st, [&] {
             return prod_c(op, nb, dh, dh_b, vh, vh_b, st);
         }));
-        BT_HIP(op, timed(op, K_C2R_M, st, [&] {
-            return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, in, prior_prec, Nt, Nm, op->plan, tw,
-                                  inv_n, st);
-        }));
+        BT_HIP(op, timed(op, K_C2R_M, st, [&] { return c2r_m(in, prior_prec); }));
         return BTOEP_OK;
     }
     // F^T
-    BT_HIP(op, timed(op, K_R2C_D, st, [&] {
-        return launch_fft_r2c(op->vreal, op->vreal, vstor(op), in, Nd, nb, dh, op->Nd, dh_b, Nt, Nd, op->plan, tw, st);
-    }));
+    BT_HIP(op, timed(op, K_R2C_D, st, [&] { return r2c_d(in); }));
     BT_HIP(op, timed(op, K_SBGEMV_C, st, [&] {
         return prod_c(op, nb, dh, dh_b, vh, vh_b, st);
     }));
-    BT_HIP(op, timed(op, K_C2R_M, st, [&] {
-        return launch_fft_c2r(op->vreal, vh, op->ldv, vh_b, nb, out, Nm, none, 0.0, Nt, Nm, op->plan, tw, inv_n, st);
-    }));
+    BT_HIP(op, timed(op, K_C2R_M, st, [&] { return c2r_m(none, 0.0); }));
     return BTOEP_OK;
 }
 
@@ -414,7 +530,6 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
     const int64_t N = choose_N(Nt);
     FftPlan plan;
     if (!make_plan(N, plan)) return BTOEP_ERR_UNSUPPORTED;
-    if (fft_log_cols((int)N, Real::F64) < 0) return BTOEP_ERR_UNSUPPORTED;
 
     btoep_op op = new (std::nothrow) btoep_op_s();
     if (!op) return BTOEP_ERR_OUT_OF_MEMORY;
@@ -468,11 +583,49 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
     BT_CREATE(hipMalloc(&op->fhat, op->fhat_bytes));
     if (op->ldF != Nm) BT_CREATE(hipMemsetAsync(op->fhat, 0, op->fhat_bytes, st));
 
+    // series too long for one workgroup: four-step transforms throughout
+    if (fft_log_cols((int)N, Real::F64) < 0) {
+        const btoep_status ls = set_long(op, 0);
+        if (ls != BTOEP_OK) return fail(ls);
+    }
+
     const size_t sb = stor_bytes(op->stor);
     const int64_t out_row = Nd * op->ldF;
+    // sensors [s0, s0 + ns) of a block column whose element (t, s, p) is at
+    // src[t * in_row + (s - s0) * Nm + p] -> Fhat rows s
+    void* ltmp = nullptr;
+    int64_t ltmp_sensors = 0;
+    auto setup_chunk = [&](const double* src, int64_t in_row, int64_t s0, int64_t ns) -> hipError_t {
+        void* dst = (char*)op->fhat + (size_t)s0 * op->ldF * sb;
+        if (!op->fft_long)
+            return launch_fft_r2c_strided(op->stor, src, in_row, Nm, (int)ns, dst, out_row, op->ldF, (int)Nt,
+                                          (int)Nm, plan, op->tw64, st);
+        for (int64_t a = 0; a < ns; a += ltmp_sensors) {
+            const int64_t n = std::min<int64_t>(ltmp_sensors, ns - a);
+            PtrBatch pb{};
+            pb.p[0] = src + a * Nm;
+            const hipError_t e = launch_long_r2c(Real::F64, Real::F64, op->stor, pb, Nm, in_row, (int)n, (int)Nt,
+                                                 (int)Nm, ltmp, Nm, N * Nm, (char*)dst + (size_t)a * op->ldF * sb,
+                                                 out_row, op->ldF, op->lp1, op->lp2, op->ltw1_64, op->ltw2_64,
+                                                 op->tw64, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    struct Free {
+        void*& p;
+        ~Free() {
+            if (p) (void)hipFree(p);
+        }
+    } free_ltmp{ltmp};
+    if (op->fft_long) {
+        // complex FP64 scratch of N rows for up to ~1 GiB of sensors at a time
+        const size_t per = (size_t)N * Nm * 16;
+        ltmp_sensors = std::max<int64_t>(1, std::min<int64_t>(Nd, (int64_t)((1ull << 30) / per)));
+        BT_CREATE(hipMalloc(&ltmp, (size_t)ltmp_sensors * per));
+    }
     if (where == BTOEP_DEVICE) {
-        BT_CREATE(launch_fft_r2c_strided(op->stor, blocks, Nd * Nm, Nm, (int)Nd, op->fhat, out_row, op->ldF, (int)Nt,
-                                         (int)Nm, plan, op->tw64, st));
+        BT_CREATE(setup_chunk(blocks, Nd * Nm, 0, Nd));
     } else {
         // stage groups of sensor rows s: [Nt][sc][Nm] FP64 at most ~1 GiB per copy
         const size_t per_s = (size_t)Nt * Nm * sizeof(double);
@@ -485,10 +638,7 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
             hipError_t e = hipMemcpy2DAsync(stage, (size_t)ns * Nm * sizeof(double), blocks + s0 * Nm,
                                             (size_t)Nd * Nm * sizeof(double), (size_t)ns * Nm * sizeof(double),
                                             (size_t)Nt, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess)
-                e = launch_fft_r2c_strided(op->stor, (const double*)stage, ns * Nm, Nm, (int)ns,
-                                           (char*)op->fhat + (size_t)s0 * op->ldF * sb, out_row, op->ldF, (int)Nt,
-                                           (int)Nm, plan, op->tw64, st);
+            if (e == hipSuccess) e = setup_chunk((const double*)stage, ns * Nm, s0, ns);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) {
                 set_err(nullptr, "staged setup", e);
@@ -511,6 +661,8 @@ btoep_status btoep_destroy(btoep_op op) {
     if (op->fhat) (void)hipFree(op->fhat);
     if (op->tw64) (void)hipFree(op->tw64);
     if (op->tw32) (void)hipFree(op->tw32);
+    for (void* q : {op->ltw1_64, op->ltw2_64, op->ltw1_32, op->ltw2_32})
+        if (q) (void)hipFree(q);
     if (op->ws) (void)hipFree(op->ws);
     for (auto& p : op->pending) {
         (void)hipEventDestroy(p.a);
@@ -786,6 +938,77 @@ btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_pr
     return all_conv ? BTOEP_OK : BTOEP_ERR_NOT_CONVERGED;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Transform mode: when a series fits one workgroup and a four-step split exists, time the
+// vector-side forward and inverse transforms of one right-hand side in each mode and keep the
+// faster.
+btoep_status tune_fft_mode(btoep_op op, int reps, hipStream_t st, btoep_tune_result* out) {
+    out->fft_four_step = op->fft_long ? 1 : 0;
+    out->ms_fft[0] = out->ms_fft[1] = 0.0;
+    FftPlan q1, q2;
+    if (fft_log_cols((int)op->N, Real::F64) < 0 || !long_split(op->N, 0, q1, q2)) return BTOEP_OK;
+    const size_t vb = (size_t)op->Nt * op->Nm * vbytes(op);
+    void* vec = nullptr;
+    BT_HIP(op, hipMalloc(&vec, 2 * vb));
+    struct Free {
+        void* p;
+        ~Free() {
+            if (p) (void)hipFree(p);
+        }
+    } free_vec{vec};
+    BT_HIP(op, hipMemsetAsync(vec, 0, 2 * vb, st));
+    PtrBatch pin{}, pout{};
+    pin.p[0] = vec;
+    pout.p[0] = (char*)vec + vb;
+    hipEvent_t a = nullptr, b = nullptr;
+    BT_HIP(op, hipEventCreate(&a));
+    BT_HIP(op, hipEventCreate(&b));
+    hipError_t e = hipSuccess;
+    btoep_status s = BTOEP_OK;
+    for (int mode = 0; mode < 2 && e == hipSuccess && s == BTOEP_OK; ++mode) {
+        (void)hipStreamSynchronize(st);
+        s = set_long(op, mode ? 0 : -1);
+        if (s != BTOEP_OK) break;
+        void* ws = nullptr;
+        size_t ws_bytes = 0;
+        s = get_ws(op, apply_layout(op, BTOEP_APPLY_H, 1).total, ws, ws_bytes);
+        if (s != BTOEP_OK) break;
+        const ApplyWs w = apply_layout(op, BTOEP_APPLY_H, 1);
+        char* base = (char*)ws;
+        auto pair = [&]() {
+            hipError_t r = vec_r2c(op, 1, pin, base + w.vh, base + w.tmp, st);
+            if (r == hipSuccess) r = vec_c2r(op, 1, base + w.vh, base + w.tmp, pout, pin, 1.0, st);
+            return r;
+        };
+        e = pair();
+        if (e == hipSuccess) e = hipEventRecord(a, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = pair();
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        out->ms_fft[mode] = (double)ms / reps;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(st);
+    const bool four = e == hipSuccess && s == BTOEP_OK && out->ms_fft[1] < out->ms_fft[0];
+    const btoep_status s2 = set_long(op, four ? 0 : -1);
+    out->fft_four_step = op->fft_long ? 1 : 0;
+    if (e != hipSuccess) {
+        set_err(op, "autotune transforms", e);
+        return BTOEP_ERR_HIP;
+    }
+    return s != BTOEP_OK ? s : s2;
+}
+
+}  // namespace
+
+extern "C" {
+
 btoep_status btoep_autotune(btoep_op op, int reps, void* stream, btoep_tune_result* out) {
     if (!op || reps < 1 || !out) return BTOEP_ERR_INVALID_ARG;
     void* ws = nullptr;
@@ -841,7 +1064,16 @@ btoep_status btoep_autotune(btoep_op op, int reps, void* stream, btoep_tune_resu
     }
     op->var_n = out->var_n;
     op->var_c = out->var_c;
-    return BTOEP_OK;
+    return tune_fft_mode(op, reps, st, out);
+}
+
+btoep_status btoep_set_fft(btoep_op op, int64_t n1) {
+    if (!op) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(op->device);
+    (void)hipDeviceSynchronize();  // no apply may still use the tables being replaced
+    const btoep_status s = set_long(op, n1 == 0 ? (fft_log_cols((int)op->N, Real::F64) < 0 ? 0 : -1) : n1);
+    if (s != BTOEP_OK && n1 != 0) (void)set_long(op, fft_log_cols((int)op->N, Real::F64) < 0 ? 0 : -1);
+    return s;
 }
 
 btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma) {

@@ -928,4 +928,339 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
     return hipGetLastError();
 }
 
+
+// ========================================================================================
+// Four-step transforms for long series (N = N1 N2): when a length-N column does not fit one
+// workgroup's LDS with a useful column tile, the half-length complex transform is split
+// (paper section 2.4 computes one length-2N DFT per series; only the order of the arithmetic
+// changes).  With n = N2 n1 + n2 and k = k1 + N1 k2,
+//   Z[k1 + N1 k2] = sum_{n2} W_{N2}^{n2 k2} W_N^{n2 k1} sum_{n1} z[N2 n1 + n2] W_{N1}^{n1 k1},
+// so pass A runs N1-point transforms (one per n2, over rows N2 n1 + n2) and applies W_N^{n2 k1},
+// pass B runs N2-point transforms (one per k1, over the contiguous rows k1 N2 + n2).  Pass B
+// transforms k1 and N1 - k1 side by side (as 2P columns), which puts every bin f next to its
+// partner N - f, so the real-to-complex split into the N + 1 bins is its epilogue.  The
+// inverse mirrors this: pass C splits, runs the N2-point inverse transforms and applies
+// W_N^{-n2 k1}; pass D runs the N1-point inverse transforms and unpacks x[2n], x[2n+1].
+// Every global access is a run of P consecutive columns of one row.  The sub-transforms use
+// the runtime plans with their own twiddle tables exp(-2 pi i t / (2 Nsub)); twN is the
+// operator's table exp(-2 pi i t / (2N)).
+
+// Input base of batch b: in.at(b), or in.at(0) + b * in_batch when in_batch != 0.
+template <typename T>
+__device__ __forceinline__ const T* batch_base(const PtrBatch& in, int64_t in_batch, int b) {
+    return in_batch ? static_cast<const T*>(in.at(0)) + (int64_t)b * in_batch : static_cast<const T*>(in.at(b));
+}
+
+// A: z[n] = x[2n] + i x[2n+1] (zero for rows >= Nt) at n = N2 n1 + n2 for one n2 (blockIdx.y);
+// forward N1-point transform over n1; times W_N^{n2 k1}; y[b][k1 N2 + n2][c].
+template <typename T, typename Tin>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_a(
+    PtrBatch in, int64_t in_batch, int64_t in_row, int Nt, int ncols, cx<T>* __restrict__ y, int64_t y_row,
+    int64_t y_batch, FftPlan p1, int N2, int logP, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ twN) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const int N1 = p1.N, P1 = (1 << logP) - 1;
+    const int col0 = blockIdx.x << logP, n2 = blockIdx.y, b = blockIdx.z;
+    const Tin* __restrict__ x = batch_base<Tin>(in, in_batch, b);
+    const int total = N1 << logP;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int c = e & P1, n1 = e >> logP;
+        const int64_t j = 2 * ((int64_t)N2 * n1 + n2);
+        const int col = min(col0 + c, ncols - 1);
+        const bool ok = col0 + c < ncols;
+        const T re = (ok && j < Nt) ? (T)x[j * in_row + col] : (T)0;
+        const T im = (ok && j + 1 < Nt) ? (T)x[(j + 1) * in_row + col] : (T)0;
+        sh[e] = cx<T>{re, im};
+    }
+    __syncthreads();
+    fft_lds<T, -1, FftCfg<T>::CMAX>(p1, logP, false, 0, tw1);
+    cx<T>* __restrict__ yb = y + (int64_t)b * y_batch;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int c = e & P1, k1 = e >> logP;
+        if (col0 + c < ncols) yb[((int64_t)k1 * N2 + n2) * y_row + col0 + c] = cmul(sh[e], twN[2 * n2 * k1]);
+    }
+}
+
+// Blocks of the paired passes: column cc < 2P of LDS holds k1 = a (block 0) or N1 - a
+// (block 1) for a = blockIdx.y; when a has no distinct partner (a == 0, 2a == N1) block 1
+// repeats block 0 and is not stored.
+__device__ __forceinline__ int pair_k1(int a, int blk, int N1) { return blk ? (N1 - a) % N1 : a; }
+
+// B: forward N2-point transforms of rows k1 N2 + n2 for k1 = a and N1 - a, then the split into
+// bins X_f = (Z_f + conj Z_{N-f}) / 2 + W_{2N}^f (Z_f - conj Z_{N-f}) / (2i), f = k1 + N1 k2.
+template <typename T, typename So>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_b(
+    const cx<T>* __restrict__ y, int64_t y_row, int64_t y_batch, So* __restrict__ out, int64_t out_row,
+    int64_t out_batch, int ncols, FftPlan p2, int N1, int logP, const cx<T>* __restrict__ tw2,
+    const cx<T>* __restrict__ twN) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const int N2 = p2.N, N = N1 * N2, P = 1 << logP, P1 = P - 1, lq = logP + 1;
+    const int col0 = blockIdx.x << logP, a = blockIdx.y, b = blockIdx.z;
+    const bool paired = a != 0 && 2 * a != N1;
+    const cx<T>* __restrict__ yb = y + (int64_t)b * y_batch;
+    const int total = N2 << lq;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int cc = e & (2 * P - 1), n2 = e >> lq;
+        const int c = cc & P1, k1 = pair_k1(a, cc >> logP, N1);
+        const int col = min(col0 + c, ncols - 1);
+        sh[e] = yb[((int64_t)k1 * N2 + n2) * y_row + col];
+    }
+    __syncthreads();
+    fft_lds<T, -1, FftCfg<T>::CMAX>(p2, lq, false, 0, tw2);
+    So* __restrict__ ob = out + (int64_t)b * out_batch;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int cc = e & (2 * P - 1), k2 = e >> lq;
+        const int blk = cc >> logP, c = cc & P1;
+        if (col0 + c >= ncols) continue;
+        const int k1 = pair_k1(a, blk, N1);
+        int f = k1 + N1 * k2;
+        if (blk == 1 && !paired) {
+            if (a != 0 || k2 != 0) continue;  // a repeated block stores nothing, except bin N
+            f = N;
+        }
+        // partner of Z_f: Z_{N-f} (Z_0 for f = 0 and f = N)
+        int prow, pblk;
+        if (k1 == 0) {
+            prow = (f == N) ? 0 : (N2 - k2) % N2;
+            pblk = blk;
+        } else {
+            prow = N2 - 1 - k2;
+            pblk = (N1 - k1 == a) ? 0 : 1;
+        }
+        const cx<T> Z = sh[((f == N ? 0 : k2) << lq) + cc];
+        const cx<T> Zc = cconj(sh[(prow << lq) + (pblk << logP) + c]);
+        const cx<T> E = cscale(cadd(Z, Zc), (T)0.5);
+        const cx<T> O = cmul_i<-1>(cscale(csub(Z, Zc), (T)0.5));
+        put_nt(&ob[(int64_t)f * out_row + col0 + c], cadd(E, cmul(twN[f], O)));
+    }
+}
+
+// C: split of the bins Y_f (f = k1 + N1 k2 for k1 = a, N1 - a; Y_N in block 1, row 0 when
+// a == 0) into Z_f = E_f + i O_f, E_f = (Y_f + conj Y_{N-f}) / 2,
+// O_f = (Y_f - conj Y_{N-f}) / 2 W_{2N}^{-f}; inverse N2-point transforms over k2; times
+// W_N^{-n2 k1}; u[b][k1 N2 + n2][c].
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_c(
+    const cx<T>* __restrict__ bins, int64_t b_row, int64_t b_batch, cx<T>* __restrict__ u, int64_t u_row,
+    int64_t u_batch, int ncols, FftPlan p2, int N1, int logP, const cx<T>* __restrict__ tw2,
+    const cx<T>* __restrict__ twN) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const int N2 = p2.N, N = N1 * N2, P = 1 << logP, P1 = P - 1, lq = logP + 1;
+    const int col0 = blockIdx.x << logP, a = blockIdx.y, b = blockIdx.z;
+    const bool paired = a != 0 && 2 * a != N1;
+    const cx<T>* __restrict__ bb = bins + (int64_t)b * b_batch;
+    const int total = N2 << lq;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int cc = e & (2 * P - 1), k2 = e >> lq;
+        const int blk = cc >> logP, c = cc & P1, k1 = pair_k1(a, blk, N1);
+        const int col = min(col0 + c, ncols - 1);
+        int f = k1 + N1 * k2;
+        if (a == 0 && blk == 1 && k2 == 0) f = N;  // Y_N, the partner of Y_0
+        sh[e] = bb[(int64_t)f * b_row + col];
+    }
+    __syncthreads();
+    // split: every element reads itself and its partner, then all write (the launcher keeps
+    // N2 x 2P <= CMAX threads, so K slots per thread hold them all)
+    constexpr int K = FftCfg<T>::CMAX;
+    cx<T> zf[K];
+#pragma unroll
+    for (int u2 = 0; u2 < K; ++u2) {
+        const int e = threadIdx.x + u2 * kFftThreads;
+        if (e < total) {
+            const int cc = e & (2 * P - 1), k2 = e >> lq;
+            const int blk = cc >> logP, c = cc & P1, k1 = pair_k1(a, blk, N1);
+            const int f = k1 + N1 * k2;
+            int prow, pblk;
+            if (k1 == 0) {
+                // partner of f = N1 k2 is N - f = N1 (N2 - k2); of f = 0 it is Y_N (block 1, row 0)
+                prow = (k2 == 0) ? 0 : N2 - k2;
+                pblk = (k2 == 0) ? 1 : blk;
+            } else {
+                prow = N2 - 1 - k2;
+                pblk = (N1 - k1 == a) ? 0 : 1;
+            }
+            const cx<T> Yf = sh[e];
+            const cx<T> Yg = cconj(sh[(prow << lq) + (pblk << logP) + c]);
+            const cx<T> E = cscale(cadd(Yf, Yg), (T)0.5);
+            const cx<T> O = cmul(cscale(csub(Yf, Yg), (T)0.5), cconj(twN[f]));
+            zf[u2] = cadd(E, cmul_i<1>(O));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u2 = 0; u2 < K; ++u2) {
+        const int e = threadIdx.x + u2 * kFftThreads;
+        if (e < total) sh[e] = zf[u2];
+    }
+    __syncthreads();
+    fft_lds<T, 1, FftCfg<T>::CMAX>(p2, lq, false, 0, tw2);
+    cx<T>* __restrict__ ub = u + (int64_t)b * u_batch;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int cc = e & (2 * P - 1), n2 = e >> lq;
+        const int blk = cc >> logP, c = cc & P1;
+        if (col0 + c >= ncols || (blk == 1 && !paired)) continue;
+        const int k1 = pair_k1(a, blk, N1);
+        ub[((int64_t)k1 * N2 + n2) * u_row + col0 + c] = cmul(sh[e], cconj(twN[2 * n2 * k1]));
+    }
+}
+
+// D: inverse N1-point transforms over k1 of rows k1 N2 + n2 for one n2 (blockIdx.y), giving
+// z[N2 n1 + n2]; out rows 2n and 2n + 1 (< Nt) = out_scale * (Re, Im) (+ add_scale * addend).
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_d(
+    const cx<T>* __restrict__ u, int64_t u_row, int64_t u_batch, PtrBatch out, int64_t out_row, PtrBatch add,
+    T add_scale, int Nt, int ncols, FftPlan p1, int N2, int logP, const cx<T>* __restrict__ tw1, T out_scale) {
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const int N1 = p1.N, P1 = (1 << logP) - 1;
+    const int col0 = blockIdx.x << logP, n2 = blockIdx.y, b = blockIdx.z;
+    const cx<T>* __restrict__ ub = u + (int64_t)b * u_batch;
+    const int total = N1 << logP;
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int c = e & P1, k1 = e >> logP;
+        sh[e] = ub[((int64_t)k1 * N2 + n2) * u_row + min(col0 + c, ncols - 1)];
+    }
+    __syncthreads();
+    fft_lds<T, 1, FftCfg<T>::CMAX>(p1, logP, false, 0, tw1);
+    T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.at(b)));
+    const T* __restrict__ ad = static_cast<const T*>(add.at(b));
+    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+        const int c = e & P1, n1 = e >> logP;
+        if (col0 + c >= ncols) continue;
+        const int64_t j = 2 * ((int64_t)N2 * n1 + n2);
+        const cx<T> z = sh[e];
+        if (j < Nt) {
+            const T v = out_scale * z.re;
+            const int64_t o = j * out_row + col0 + c;
+            x[o] = ad ? fma(add_scale, ad[o], v) : v;
+        }
+        if (j + 1 < Nt) {
+            const T v = out_scale * z.im;
+            const int64_t o = (j + 1) * out_row + col0 + c;
+            x[o] = ad ? fma(add_scale, ad[o], v) : v;
+        }
+    }
+}
+
+// Data side of the long path: part[b][s][f][span] summed over spans into spec[b][f][s].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_spans(const cx<T>* __restrict__ part, int nspan, int64_t part_batch,
+                                                   cx<T>* __restrict__ spec, int64_t spec_batch, int nfreq, int Nd) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)nfreq * Nd) return;
+    const int f = (int)(e / Nd), s = (int)(e % Nd);
+    const cx<T>* q = part + (int64_t)blockIdx.y * part_batch + ((int64_t)s * nfreq + f) * nspan;
+    cx<T> acc = cx<T>{0, 0};
+    for (int sp = 0; sp < nspan; ++sp) acc = cadd(acc, q[sp]);
+    spec[(int64_t)blockIdx.y * spec_batch + e] = acc;
+}
+
+
+// ---- four-step launchers -------------------------------------------------------------------
+// Widest column tile (log2) for the passes of N = N1 N2: N1 x P (passes A, D) and N2 x 2P
+// (passes B, C) complex values in LDS and per CMAX threads; -1 when not even one column fits.
+int long_log_cols(int N1, int N2, Real r) {
+    const size_t elem = elem_of(r);
+    for (int lp = 6; lp >= 0; --lp) {
+        const size_t P = (size_t)1 << lp;
+        const size_t a = (size_t)N1 * P, b = (size_t)N2 * 2 * P;
+        if (a * elem <= kFftLdsBudget && b * elem <= kFftLdsBudget && a <= (size_t)cmax_of(r) * kFftThreads &&
+            b <= (size_t)cmax_of(r) * kFftThreads)
+            return lp;
+    }
+    return -1;
+}
+
+static int long_pick_cols(int N1, int N2, Real r, int ncols, int nb) {
+    int lp = long_log_cols(N1, N2, r);
+    while (lp > 0 && (int64_t)nblk(ncols, lp) * nb * N2 < 2048) --lp;
+    return lp;
+}
+
+hipError_t launch_long_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_batch, int64_t in_row, int nb,
+                           int Nt, int ncols, void* tmp, int64_t tmp_row, int64_t tmp_batch, void* out,
+                           int64_t out_row, int64_t out_batch, const FftPlan& p1, const FftPlan& p2, const void* tw1,
+                           const void* tw2, const void* twN, hipStream_t st) {
+    const int N1 = p1.N, N2 = p2.N;
+    const int lp = long_pick_cols(N1, N2, r, ncols, nb);
+    if (lp < 0 || nb <= 0 || nb > 65535 || N2 > 65535 || tmp_row < ncols) return hipErrorInvalidValue;
+    const unsigned nt = nblk(ncols, lp);
+    const size_t elem = elem_of(r);
+    const size_t lds_a = ((size_t)N1 << lp) * elem, lds_b = ((size_t)N2 << (lp + 1)) * elem;
+    dim3 ga(nt, N2, nb), gb(nt, N1 / 2 + 1, nb), block(kFftThreads);
+    if (r == Real::F32 && ir == Real::F32 && os == Stor::C64) {
+        k_long_a<float, float><<<ga, block, lds_a, st>>>(in, in_batch, in_row, Nt, ncols, (cx<float>*)tmp, tmp_row,
+                                                         tmp_batch, p1, N2, lp, (const cx<float>*)tw1,
+                                                         (const cx<float>*)twN);
+        k_long_b<float, cx<float>><<<gb, block, lds_b, st>>>((const cx<float>*)tmp, tmp_row, tmp_batch,
+                                                             (cx<float>*)out, out_row, out_batch, ncols, p2, N1, lp,
+                                                             (const cx<float>*)tw2, (const cx<float>*)twN);
+    } else if (r == Real::F64 && ir == Real::F64) {
+        k_long_a<double, double><<<ga, block, lds_a, st>>>(in, in_batch, in_row, Nt, ncols, (cx<double>*)tmp,
+                                                           tmp_row, tmp_batch, p1, N2, lp, (const cx<double>*)tw1,
+                                                           (const cx<double>*)twN);
+        const cx<double>* t = (const cx<double>*)tmp;
+        const cx<double>* w2 = (const cx<double>*)tw2;
+        const cx<double>* wN = (const cx<double>*)twN;
+        switch (os) {
+            case Stor::C128:
+                k_long_b<double, cx<double>><<<gb, block, lds_b, st>>>(t, tmp_row, tmp_batch, (cx<double>*)out,
+                                                                       out_row, out_batch, ncols, p2, N1, lp, w2, wN);
+                break;
+            case Stor::C64:
+                k_long_b<double, cx<float>><<<gb, block, lds_b, st>>>(t, tmp_row, tmp_batch, (cx<float>*)out,
+                                                                      out_row, out_batch, ncols, p2, N1, lp, w2, wN);
+                break;
+            case Stor::BF16:
+                k_long_b<double, bf16c><<<gb, block, lds_b, st>>>(t, tmp_row, tmp_batch, (bf16c*)out, out_row,
+                                                                  out_batch, ncols, p2, N1, lp, w2, wN);
+                break;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_long_c2r(Real r, const void* in, int64_t in_row, int64_t in_batch, int nb, void* tmp,
+                           int64_t tmp_row, int64_t tmp_batch, const PtrBatch& out, int64_t out_row,
+                           const PtrBatch& add, double add_scale, int Nt, int ncols, const FftPlan& p1,
+                           const FftPlan& p2, const void* tw1, const void* tw2, const void* twN, double out_scale,
+                           hipStream_t st) {
+    const int N1 = p1.N, N2 = p2.N;
+    const int lp = long_pick_cols(N1, N2, r, ncols, nb);
+    if (lp < 0 || nb <= 0 || nb > 65535 || N2 > 65535 || tmp_row < ncols) return hipErrorInvalidValue;
+    const unsigned nt = nblk(ncols, lp);
+    const size_t elem = elem_of(r);
+    const size_t lds_d = ((size_t)N1 << lp) * elem, lds_c = ((size_t)N2 << (lp + 1)) * elem;
+    dim3 gc(nt, N1 / 2 + 1, nb), gd(nt, N2, nb), block(kFftThreads);
+    if (r == Real::F32) {
+        k_long_c<float><<<gc, block, lds_c, st>>>((const cx<float>*)in, in_row, in_batch, (cx<float>*)tmp, tmp_row,
+                                                  tmp_batch, ncols, p2, N1, lp, (const cx<float>*)tw2,
+                                                  (const cx<float>*)twN);
+        k_long_d<float><<<gd, block, lds_d, st>>>((const cx<float>*)tmp, tmp_row, tmp_batch, out, out_row, add,
+                                                  (float)add_scale, Nt, ncols, p1, N2, lp, (const cx<float>*)tw1,
+                                                  (float)out_scale);
+    } else {
+        k_long_c<double><<<gc, block, lds_c, st>>>((const cx<double>*)in, in_row, in_batch, (cx<double>*)tmp,
+                                                   tmp_row, tmp_batch, ncols, p2, N1, lp, (const cx<double>*)tw2,
+                                                   (const cx<double>*)twN);
+        k_long_d<double><<<gd, block, lds_d, st>>>((const cx<double>*)tmp, tmp_row, tmp_batch, out, out_row, add,
+                                                   add_scale, Nt, ncols, p1, N2, lp, (const cx<double>*)tw1,
+                                                   out_scale);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_spans(Real r, const void* part, int nspan, int64_t part_batch, void* spec, int64_t spec_batch,
+                            int nfreq, int Nd, int nb, hipStream_t st) {
+    if (nb <= 0 || nb > 65535) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(((int64_t)nfreq * Nd + 255) / 256), nb);
+    if (r == Real::F32)
+        k_sum_spans<float><<<grid, 256, 0, st>>>((const cx<float>*)part, nspan, part_batch, (cx<float>*)spec,
+                                                 spec_batch, nfreq, Nd);
+    else
+        k_sum_spans<double><<<grid, 256, 0, st>>>((const cx<double>*)part, nspan, part_batch, (cx<double>*)spec,
+                                                  spec_batch, nfreq, Nd);
+    return hipGetLastError();
+}
+
 }  // namespace btoep

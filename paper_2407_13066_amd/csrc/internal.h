@@ -61,6 +61,25 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
                         const PtrBatch* dout, void* dh, int64_t dh_batch, int Nt, int Nd,
                         const FftPlan& plan, const void* tw, double scale, hipStream_t st);
 
+// ---- four-step transforms for long series (fft.hip) ------------------------------------
+// N = N1 N2 (plans p1, p2; sub-twiddle tables tw1, tw2 of exp(-2 pi i t / (2 Nsub)), t < 2 Nsub;
+// twN the operator's table).  Same inputs and outputs as launch_fft_r2c / launch_fft_c2r plus
+// a complex scratch tmp[b][N][tmp_row] (tmp_row >= ncols).  The forward input of batch b is
+// in.at(b), or in.at(0) + b * in_batch when in_batch != 0 (setup: sensors of a block column).
+int long_log_cols(int N1, int N2, Real r);
+hipError_t launch_long_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_batch, int64_t in_row, int nb,
+                           int Nt, int ncols, void* tmp, int64_t tmp_row, int64_t tmp_batch, void* out,
+                           int64_t out_row, int64_t out_batch, const FftPlan& p1, const FftPlan& p2, const void* tw1,
+                           const void* tw2, const void* twN, hipStream_t st);
+hipError_t launch_long_c2r(Real r, const void* in, int64_t in_row, int64_t in_batch, int nb, void* tmp,
+                           int64_t tmp_row, int64_t tmp_batch, const PtrBatch& out, int64_t out_row,
+                           const PtrBatch& add, double add_scale, int Nt, int ncols, const FftPlan& p1,
+                           const FftPlan& p2, const void* tw1, const void* tw2, const void* twN, double out_scale,
+                           hipStream_t st);
+// Partial sums part[b][s][f][span] summed over spans into spec[b][f][s].
+hipError_t launch_sum_spans(Real r, const void* part, int nspan, int64_t part_batch, void* spec, int64_t spec_batch,
+                            int nfreq, int Nd, int nb, hipStream_t st);
+
 // ---- launchers (sbgemv.hip) ---------------------------------------------------------
 // Per-frequency products with the stored operator Fh[f][s][p] (row stride ldF, frequency
 // stride Nd*ldF).  N: part[b][s][f][span] = sum_{p in span} Fh[f][s][p] mh[b][f][p].

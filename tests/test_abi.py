@@ -56,6 +56,7 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     assert lib.btoep_query(None, None) == 1
     assert lib.btoep_graph_launch(None, None, None, None) == 1
     assert lib.btoep_graph_destroy(None) == 1
+    assert lib.btoep_set_fft(None, 0) == 1
     g = ctypes.c_void_p()
     assert lib.btoep_graph_create(None, 2, 1, 1.0, 1.0, ctypes.c_void_p(8), 1 << 20, ctypes.byref(g)) == 1
     assert lib.btoep_graph_create(None, 2, 1, 1.0, 1.0, None, 0, None) == 1

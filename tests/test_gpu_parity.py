@@ -200,9 +200,19 @@ def test_query_and_workspace(bt):
         bt.btoep_apply_F(op, torch.zeros((420, 17), dtype=torch.float32, device="cuda"), ws=ws)
 
 
-def test_unsupported_length_is_an_error(bt):
+def test_long_series_supported_and_overlong_refused(bt):
+    """Nt = 5000 does not fit one workgroup in FP64 (four-step transforms take over); beyond
+    2^20 steps create refuses."""
+    rng = np.random.default_rng(9)
+    blocks = rng.standard_normal((5000, 1, 1)) * np.exp(-np.arange(5000) / 700.0)[:, None, None]
+    m = rng.standard_normal((5000, 1))
+    op = bt.btoep_create(blocks, "f64")
+    d = bt.btoep_apply_F(op, to_dev(m, torch.float64))
+    torch.cuda.synchronize()
+    ref = np.convolve(blocks[:, 0, 0], m[:, 0])[:5000]
+    assert oracle.rel_l2(d.cpu().numpy()[:, 0], ref) <= 1e-12
     with pytest.raises(bt.BtoepError):
-        bt.btoep_create(np.zeros((5000, 1, 1)), "f64")
+        bt.btoep_create(np.zeros(((1 << 20) + 1, 1, 1)), "f64")
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
