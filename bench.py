@@ -323,6 +323,36 @@ def paper_shapes_benchmark(bt):
     return out
 
 
+def setup_benchmark(bt, blocks, storage, host_s):
+    """Setup of the stored operator (transform of every block series, Alg. 1 on one device) from
+    device-resident FP64 blocks, given as the first block column and as the last block row; the
+    host-input setup time of the main operator (PCIe-bound staging included) for context.
+    Algorithmic bytes: the FP64 blocks read once plus the stored spectra written once."""
+    import torch
+    Nt, Nd, Nm = blocks.shape
+    dev_blocks = torch.from_numpy(blocks).cuda()
+    op = bt.btoep_create_empty(Nt, Nd, Nm, storage)
+    sb = {"f64": 16, "f32": 8, "bf16": 4}[storage]
+    nbytes = blocks.nbytes + op.info["nfreq"] * Nd * Nm * sb
+    out = {"host_create_s": round(host_s, 3), "algorithmic_GB": round(nbytes / 1e9, 2)}
+    for order, src in (("column", dev_blocks), ("last_row", None)):
+        if src is None:
+            src = torch.flip(dev_blocks, [0])
+            del dev_blocks
+        bt.btoep_set_blocks(op, 0, 0, src, order=order)  # warm-up (returns when done)
+        t = time.perf_counter()
+        bt.btoep_set_blocks(op, 0, 0, src, order=order)
+        ms = (time.perf_counter() - t) * 1e3
+        out["device_%s_ms" % order] = round(ms, 2)
+        out["device_%s_GBs" % order] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+        del src
+    log("setup: host %.2f s; device block column %.1f ms (%.0f GB/s), last block row %.1f ms" % (
+        host_s, out["device_column_ms"], out["device_column_GBs"], out["device_last_row_ms"]))
+    op.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cg_benchmark(bt):
     """Inverse-problem CG: H = sigma^-2 F^T F + alpha I with sigma = 1e-2, alpha = 1e-3 on
     Nt=256, Nd=64, Nm=16384 (blocks N(0,1) exp(-k/(Nt/7))), d = F m_true + N(0, sigma^2),
@@ -390,6 +420,7 @@ def main():
                     help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solve measurement")
     ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape (FP64) context runs")
+    ap.add_argument("--no-setup", action="store_true", help="skip the setup (block transform) measurement")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
                     help="parameter columns of the operator the CPU oracle is timed on")
     args = ap.parse_args()
@@ -432,7 +463,9 @@ def main():
     blocks = synth.blocks(Nt, Nd, Nm, tau)
     m_host = synth.vectors(1, Nt, Nm, synth.STREAM_M)[0]
     log("creating operator (FP32 complex storage)")
+    t_setup = time.perf_counter()
     op = bt.btoep_create(blocks, w["storage"])
+    host_setup_s = time.perf_counter() - t_setup
     info = bt.btoep_query(op)
     log("operator: L=%d nfreq=%d fhat=%.2f GB" % (info["L"], info["nfreq"], info["fhat_bytes"] / 1e9))
 
@@ -570,8 +603,10 @@ def main():
         result["multi_rhs"] = multi_rhs_benchmark(bt, blocks, op, ks, ms_per_step)
 
     op.destroy()
-    del blocks
     torch.cuda.empty_cache()
+    if not args.no_setup:
+        result["setup"] = setup_benchmark(bt, blocks, w["storage"], host_setup_s)
+    del blocks
     if not args.no_cg:
         result["cg"] = cg_benchmark(bt)
         torch.cuda.empty_cache()

@@ -45,7 +45,8 @@ typedef enum {
     BTOEP_ERR_HIP = 3,
     BTOEP_ERR_UNSUPPORTED = 4,
     BTOEP_ERR_NOT_CONVERGED = 5,
-    BTOEP_ERR_WORKSPACE_TOO_SMALL = 6
+    BTOEP_ERR_WORKSPACE_TOO_SMALL = 6,
+    BTOEP_ERR_IO = 7
 } btoep_status;
 
 /* Storage precision of the Fourier-space operator (complex FP64, FP32 or BF16 parts). */
@@ -82,11 +83,58 @@ typedef struct {
  *            device memory per `where`.  Not retained; may be freed once the call returns.
  *   stream : stream for the setup work; the call returns after it has completed.
  *   out    : receives the new operator (owned by the caller; free with btoep_destroy).
- * Uses the current HIP device.  Errors: INVALID_ARG (sizes < 1, null pointers),
- * UNSUPPORTED (transform length beyond one workgroup: N > 4095), OUT_OF_MEMORY, HIP.
+ * Uses the current HIP device.  Series too long for one workgroup's local memory use the
+ * four-step transforms (see btoep_set_fft).  Errors: INVALID_ARG (sizes < 1, null pointers),
+ * UNSUPPORTED (Nt > 2^20, Nd > 65535, Nm > 2^30), OUT_OF_MEMORY, HIP.
  */
 btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* blocks, btoep_memory where,
                           btoep_dtype storage, void* stream, btoep_op* out);
+
+/*
+ * Setup in pieces (paper section 3.2, Algorithm 1: each processor reads and transforms its
+ * own rectangle of sensor rows x parameter columns of the block matrix).
+ *
+ * btoep_create_empty makes an operator of the given shape whose stored Fhat is zero (F = 0);
+ * btoep_set_blocks then transforms and stores any rectangle of it, replacing what was there.
+ * Every (sensor, parameter) series is transformed on its own, so setting all rectangles of a
+ * partition, in any order, stores exactly (bit for bit) what btoep_create stores.  Applies
+ * may run between calls; they see zero blocks where nothing was set.
+ *
+ * The block sequence may be given as the first block column (order BTOEP_BLOCK_COLUMN:
+ * input time t holds F_t, what Nm forward solves produce) or as the last block row
+ * (BTOEP_LAST_BLOCK_ROW: input time t holds F_{Nt-1-t}, what Nd adjoint solves produce;
+ * section 2.3 notes that either determines F).
+ *   s0, ns : sensor rows s0 .. s0+ns-1;  p0, np : parameter columns p0 .. p0+np-1
+ *   src    : FP64, element (t, s, p) at src[t*ld_time + (s-s0)*ld_sensor + (p-p0)], t < Nt,
+ *            host or device memory per `where`; not retained.  ld_sensor >= np and
+ *            ld_time >= (ns-1)*ld_sensor + np (rows do not overlap).
+ *   stream : stream for the work; the call returns after it has completed.
+ * Errors: INVALID_ARG (rectangle outside the operator, bad strides or enums, null
+ * pointers), OUT_OF_MEMORY, HIP.
+ */
+typedef enum { BTOEP_BLOCK_COLUMN = 0, BTOEP_LAST_BLOCK_ROW = 1 } btoep_block_order;
+
+btoep_status btoep_create_empty(int64_t Nt, int64_t Nd, int64_t Nm, btoep_dtype storage, void* stream,
+                                btoep_op* out);
+btoep_status btoep_set_blocks(btoep_op op, int64_t s0, int64_t ns, int64_t p0, int64_t np, const double* src,
+                              int64_t ld_time, int64_t ld_sensor, btoep_block_order order, btoep_memory where,
+                              void* stream);
+
+/*
+ * Keeping the transformed operator for reuse (section 3.2: the setup output is stored for
+ * later matvecs).  btoep_save writes Fhat as stored -- a 64-byte little-endian header (magic
+ * "BTOEPFH\n", version 1, storage code, Nt, Nd, Nm, L, payload bytes) followed by
+ * Fhat[f][s][p], f <= L/2, s < Nd, p < Nm, in the storage format -- and btoep_load makes a new
+ * operator on the current device holding exactly those values (applies then return the same
+ * bits as on the saved operator, for the same transform mode and tuning).  Both copy
+ * through a 64 MiB pinned host buffer and return when done.
+ * Errors: INVALID_ARG (null pointers), IO (the file cannot be opened, read or written; a
+ * header that is not this format, names sizes outside the library's limits or a transform
+ * length the library would not choose for Nt, or a file size that does not match it --
+ * all checked before any device work), OUT_OF_MEMORY, HIP.
+ */
+btoep_status btoep_save(btoep_op op, const char* path, void* stream);
+btoep_status btoep_load(const char* path, void* stream, btoep_op* out);
 
 /* Releases the operator and everything it owns (synchronises its device). */
 btoep_status btoep_destroy(btoep_op op);

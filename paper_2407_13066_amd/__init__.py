@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libbtoep.so")
 
 BTOEP_OK = 0
 BTOEP_ERR_NOT_CONVERGED = 5
+BTOEP_ERR_IO = 7
+ORDER = {"column": 0, "last_row": 1}
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 WHICH = {"F": 0, "FT": 1, "H": 2, "CG": 3}
 MAX_BATCH = 64
@@ -73,6 +75,10 @@ def load_library(path=LIB_PATH):
     st = ctypes.c_int
     sig = {
         "btoep_create": ([i64, i64, i64, vp, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)], st),
+        "btoep_create_empty": ([i64, i64, i64, ctypes.c_int, vp, ctypes.POINTER(vp)], st),
+        "btoep_set_blocks": ([vp, i64, i64, i64, i64, vp, i64, i64, ctypes.c_int, ctypes.c_int, vp], st),
+        "btoep_save": ([vp, ctypes.c_char_p, vp], st),
+        "btoep_load": ([ctypes.c_char_p, vp, ctypes.POINTER(vp)], st),
         "btoep_destroy": ([vp], st),
         "btoep_query": ([vp, ctypes.POINTER(_Info)], st),
         "btoep_workspace_size": ([vp, ctypes.c_int, i64, ctypes.POINTER(sz)], st),
@@ -186,6 +192,58 @@ def btoep_create(blocks, storage="f32", stream=None):
                           ctypes.byref(h))
     del keep
     _check(st, "btoep_create")
+    return Op(h, btoep_query(h))
+
+
+def btoep_create_empty(Nt, Nd, Nm, storage="f32", stream=None):
+    """An operator of the given shape with all blocks zero; fill it with btoep_set_blocks."""
+    h = ctypes.c_void_p()
+    _check(load_library().btoep_create_empty(int(Nt), int(Nd), int(Nm), STORAGE[storage], _stream(stream),
+                                             ctypes.byref(h)), "btoep_create_empty")
+    return Op(h, btoep_query(h))
+
+
+def btoep_set_blocks(op, s0, p0, blocks, order="column", stream=None):
+    """Transform and store sensors s0.. x parameters p0.. from ``blocks`` [Nt][ns][np] (FP64).
+
+    ``order`` "column": blocks[t] = F_t (first block column); "last_row": blocks[t] = F_{Nt-1-t}
+    (last block row).  ``blocks`` is a numpy array or a torch float64 tensor (host or device),
+    possibly a strided view whose last axis is contiguous.
+    """
+    import numpy as np
+    torch = _torch()
+    if isinstance(blocks, np.ndarray):
+        if blocks.dtype != np.float64:
+            raise ValueError("blocks must be float64")
+        if blocks.ndim != 3 or blocks.strides[2] != 8 or blocks.strides[0] % 8 or blocks.strides[1] % 8:
+            raise ValueError("blocks must be [Nt][ns][np] with a contiguous last axis")
+        ptr, where, shape = blocks.ctypes.data, 0, blocks.shape
+        ld_t, ld_s = blocks.strides[0] // 8, blocks.strides[1] // 8
+    else:
+        t = blocks
+        if t.dtype != torch.float64 or t.dim() != 3 or t.stride(2) != 1:
+            raise ValueError("blocks must be a float64 [Nt][ns][np] tensor with a contiguous last axis")
+        ptr, where, shape = t.data_ptr(), (1 if t.is_cuda else 0), tuple(t.shape)
+        ld_t, ld_s = t.stride(0), t.stride(1)
+    if shape[0] != op.Nt:
+        raise ValueError("blocks has %d time rows, the operator %d" % (shape[0], op.Nt))
+    ns, np_ = shape[1], shape[2]
+    if ns == 1:
+        ld_s = max(ld_s, np_)
+    _check(load_library().btoep_set_blocks(op.handle, int(s0), int(ns), int(p0), int(np_), ctypes.c_void_p(ptr),
+                                           int(ld_t), int(ld_s), ORDER[order], where, _stream(stream)),
+           "btoep_set_blocks", op.handle)
+
+
+def btoep_save(op, path, stream=None):
+    """Write the stored Fourier-space operator to ``path``."""
+    _check(load_library().btoep_save(op.handle, os.fsencode(path), _stream(stream)), "btoep_save", op.handle)
+
+
+def btoep_load(path, stream=None):
+    """A new operator holding the Fourier-space operator saved in ``path``."""
+    h = ctypes.c_void_p()
+    _check(load_library().btoep_load(os.fsencode(path), _stream(stream), ctypes.byref(h)), "btoep_load")
     return Op(h, btoep_query(h))
 
 

@@ -500,32 +500,14 @@ btoep_status apply_contig(btoep_op op, btoep_which which, int64_t k, const void*
     return BTOEP_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* btoep_status_string(btoep_status s) {
-    switch (s) {
-        case BTOEP_OK: return "ok";
-        case BTOEP_ERR_INVALID_ARG: return "invalid argument";
-        case BTOEP_ERR_OUT_OF_MEMORY: return "out of device memory";
-        case BTOEP_ERR_HIP: return "HIP runtime error";
-        case BTOEP_ERR_UNSUPPORTED: return "unsupported shape or option";
-        case BTOEP_ERR_NOT_CONVERGED: return "CG did not converge";
-        case BTOEP_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
-    }
-    return "unknown status";
-}
-
-const char* btoep_last_error(btoep_op op) { return op ? op->err : g_err; }
-
-btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* blocks, btoep_memory where,
-                          btoep_dtype storage, void* stream, btoep_op* out) {
-    if (!out) return BTOEP_ERR_INVALID_ARG;
+// ---- setup ---------------------------------------------------------------------------
+// Operator without its Fourier-space blocks: shapes, plans, twiddle tables and the storage of
+// Fhat, zeroed when `zero` (otherwise only the alignment padding of each row is cleared).
+btoep_status create_shell(int64_t Nt, int64_t Nd, int64_t Nm, btoep_dtype storage, bool zero, hipStream_t st,
+                          btoep_op* out) {
     *out = nullptr;
-    if (Nt < 1 || Nd < 1 || Nm < 1 || !blocks) return BTOEP_ERR_INVALID_ARG;
+    if (Nt < 1 || Nd < 1 || Nm < 1) return BTOEP_ERR_INVALID_ARG;
     if (storage != BTOEP_F64 && storage != BTOEP_F32 && storage != BTOEP_BF16) return BTOEP_ERR_INVALID_ARG;
-    if (where != BTOEP_HOST && where != BTOEP_DEVICE) return BTOEP_ERR_INVALID_ARG;
     if (Nd > 65535 || Nm > ((int64_t)1 << 30) || Nt > ((int64_t)1 << 20)) return BTOEP_ERR_UNSUPPORTED;
     const int64_t N = choose_N(Nt);
     FftPlan plan;
@@ -549,18 +531,18 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
     op->stor = storage == BTOEP_F64 ? Stor::C128 : (storage == BTOEP_F32 ? Stor::C64 : Stor::BF16);
     op->vreal = storage == BTOEP_F64 ? Real::F64 : Real::F32;
     op->plan = plan;
-    hipStream_t st = (hipStream_t)stream;
     auto fail = [&](btoep_status s) {
+        snprintf(g_err, sizeof g_err, "%s", op->err);
         btoep_destroy(op);
         return s;
     };
-#define BT_CREATE(expr)                                              \
-    do {                                                             \
-        hipError_t e_ = (expr);                                      \
-        if (e_ != hipSuccess) {                                      \
-            set_err(nullptr, #expr, e_);                             \
+#define BT_SHELL(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_err(op, #expr, e_);                                                         \
             return fail(e_ == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP); \
-        }                                                            \
+        }                                                                                   \
     } while (0)
 
     // twiddles exp(-2 pi i t / L), t < L, from FP64 cos / sin
@@ -574,44 +556,41 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
         t32[2 * t] = (float)t64[2 * t];
         t32[2 * t + 1] = (float)t64[2 * t + 1];
     }
-    BT_CREATE(hipMalloc(&op->tw64, t64.size() * sizeof(double)));
-    BT_CREATE(hipMalloc(&op->tw32, t32.size() * sizeof(float)));
-    BT_CREATE(hipMemcpy(op->tw64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
-    BT_CREATE(hipMemcpy(op->tw32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+    BT_SHELL(hipMalloc(&op->tw64, t64.size() * sizeof(double)));
+    BT_SHELL(hipMalloc(&op->tw32, t32.size() * sizeof(float)));
+    BT_SHELL(hipMemcpy(op->tw64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    BT_SHELL(hipMemcpy(op->tw32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
 
     op->fhat_bytes = (size_t)op->nfreq * Nd * op->ldF * stor_bytes(op->stor);
-    BT_CREATE(hipMalloc(&op->fhat, op->fhat_bytes));
-    if (op->ldF != Nm) BT_CREATE(hipMemsetAsync(op->fhat, 0, op->fhat_bytes, st));
+    BT_SHELL(hipMalloc(&op->fhat, op->fhat_bytes));
+    if (zero || op->ldF != Nm) BT_SHELL(hipMemsetAsync(op->fhat, 0, op->fhat_bytes, st));
+    BT_SHELL(hipStreamSynchronize(st));
+#undef BT_SHELL
 
     // series too long for one workgroup: four-step transforms throughout
     if (fft_log_cols((int)N, Real::F64) < 0) {
         const btoep_status ls = set_long(op, 0);
         if (ls != BTOEP_OK) return fail(ls);
     }
+    *out = op;
+    return BTOEP_OK;
+}
 
+// Transforms the series of sensors [s0, s0+ns) x parameters [p0, p0+np) and stores them in
+// Fhat[f][s][p0 ..].  Element (t, s, p) of the input is src[t*ld_time + (s-s0)*ld_sensor +
+// (p-p0)], read for t = 0 .. Nt-1 as F_t (block column) or as F_{Nt-1-t} (last block row);
+// the kernels read the latter from its last time row with a negative row stride.  Host input
+// is staged through device memory in groups of sensors of at most ~1 GiB.  Returns after the
+// work has completed.
+btoep_status fill_tile(btoep_op op, int64_t s0, int64_t ns, int64_t p0, int64_t np, const double* src,
+                       int64_t ld_time, int64_t ld_sensor, btoep_block_order order, btoep_memory where,
+                       hipStream_t st) {
+    const int64_t Nt = op->Nt, N = op->N;
     const size_t sb = stor_bytes(op->stor);
-    const int64_t out_row = Nd * op->ldF;
-    // sensors [s0, s0 + ns) of a block column whose element (t, s, p) is at
-    // src[t * in_row + (s - s0) * Nm + p] -> Fhat rows s
+    const int64_t out_row = op->Nd * op->ldF;
+    const bool rev = order == BTOEP_LAST_BLOCK_ROW;
     void* ltmp = nullptr;
     int64_t ltmp_sensors = 0;
-    auto setup_chunk = [&](const double* src, int64_t in_row, int64_t s0, int64_t ns) -> hipError_t {
-        void* dst = (char*)op->fhat + (size_t)s0 * op->ldF * sb;
-        if (!op->fft_long)
-            return launch_fft_r2c_strided(op->stor, src, in_row, Nm, (int)ns, dst, out_row, op->ldF, (int)Nt,
-                                          (int)Nm, plan, op->tw64, st);
-        for (int64_t a = 0; a < ns; a += ltmp_sensors) {
-            const int64_t n = std::min<int64_t>(ltmp_sensors, ns - a);
-            PtrBatch pb{};
-            pb.p[0] = src + a * Nm;
-            const hipError_t e = launch_long_r2c(Real::F64, Real::F64, op->stor, pb, Nm, in_row, (int)n, (int)Nt,
-                                                 (int)Nm, ltmp, Nm, N * Nm, (char*)dst + (size_t)a * op->ldF * sb,
-                                                 out_row, op->ldF, op->lp1, op->lp2, op->ltw1_64, op->ltw2_64,
-                                                 op->tw64, st);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
     struct Free {
         void*& p;
         ~Free() {
@@ -620,38 +599,240 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
     } free_ltmp{ltmp};
     if (op->fft_long) {
         // complex FP64 scratch of N rows for up to ~1 GiB of sensors at a time
-        const size_t per = (size_t)N * Nm * 16;
-        ltmp_sensors = std::max<int64_t>(1, std::min<int64_t>(Nd, (int64_t)((1ull << 30) / per)));
-        BT_CREATE(hipMalloc(&ltmp, (size_t)ltmp_sensors * per));
+        const size_t per = (size_t)N * np * 16;
+        ltmp_sensors = std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)((1ull << 30) / per)));
+        BT_HIP(op, hipMalloc(&ltmp, (size_t)ltmp_sensors * per));
     }
-    if (where == BTOEP_DEVICE) {
-        BT_CREATE(setup_chunk(blocks, Nd * Nm, 0, Nd));
-    } else {
-        // stage groups of sensor rows s: [Nt][sc][Nm] FP64 at most ~1 GiB per copy
-        const size_t per_s = (size_t)Nt * Nm * sizeof(double);
-        int64_t sc = std::max<int64_t>(1, std::min<int64_t>(Nd, (int64_t)((1ull << 30) / per_s)));
-        sc = std::min<int64_t>(sc, 65535);
-        void* stage = nullptr;
-        BT_CREATE(hipMalloc(&stage, (size_t)sc * per_s));
-        for (int64_t s0 = 0; s0 < Nd; s0 += sc) {
-            const int64_t ns = std::min<int64_t>(sc, Nd - s0);
-            hipError_t e = hipMemcpy2DAsync(stage, (size_t)ns * Nm * sizeof(double), blocks + s0 * Nm,
-                                            (size_t)Nd * Nm * sizeof(double), (size_t)ns * Nm * sizeof(double),
-                                            (size_t)Nt, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = setup_chunk((const double*)stage, ns * Nm, s0, ns);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) {
-                set_err(nullptr, "staged setup", e);
-                (void)hipFree(stage);
-                return fail(e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP);
-            }
+    // sensors [s, s+n) whose time row 0 (in block-column order) starts at `first`
+    auto run = [&](const double* first, int64_t in_row, int64_t in_batch, int64_t s, int64_t n) -> hipError_t {
+        char* dst = (char*)op->fhat + ((size_t)s * op->ldF + (size_t)p0) * sb;
+        if (!op->fft_long)
+            return launch_fft_r2c_strided(op->stor, first, in_row, in_batch, (int)n, dst, out_row, op->ldF, (int)Nt,
+                                          (int)np, op->plan, op->tw64, st);
+        for (int64_t a = 0; a < n; a += ltmp_sensors) {
+            const int64_t c = std::min<int64_t>(ltmp_sensors, n - a);
+            PtrBatch pb{};
+            pb.p[0] = first + a * in_batch;
+            const hipError_t e = launch_long_r2c(Real::F64, Real::F64, op->stor, pb, in_batch, in_row, (int)c,
+                                                 (int)Nt, (int)np, ltmp, np, N * np, dst + (size_t)a * op->ldF * sb,
+                                                 out_row, op->ldF, op->lp1, op->lp2, op->ltw1_64, op->ltw2_64,
+                                                 op->tw64, st);
+            if (e != hipSuccess) return e;
         }
-        (void)hipFree(stage);
+        return hipSuccess;
+    };
+    if (where == BTOEP_DEVICE) {
+        const double* first = rev ? src + (Nt - 1) * ld_time : src;
+        BT_HIP(op, run(first, rev ? -ld_time : ld_time, ld_sensor, s0, ns));
+        BT_HIP(op, hipStreamSynchronize(st));
+        return BTOEP_OK;
     }
-    BT_CREATE(hipStreamSynchronize(st));
-#undef BT_CREATE
+    // host: groups of sensors copied as [Nt][sc][np] FP64
+    const size_t per_s = (size_t)Nt * np * sizeof(double);
+    const int64_t sc = std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)((1ull << 30) / per_s)));
+    double* stage = nullptr;
+    BT_HIP(op, hipMalloc((void**)&stage, (size_t)sc * per_s));
+    struct FreeStage {
+        double*& p;
+        ~FreeStage() { (void)hipFree(p); }
+    } free_stage{stage};
+    for (int64_t a = 0; a < ns; a += sc) {
+        const int64_t n = std::min<int64_t>(sc, ns - a);
+        const size_t dpitch = (size_t)n * np * sizeof(double), spitch = (size_t)ld_time * sizeof(double);
+        if (ld_sensor == np) {
+            BT_HIP(op, hipMemcpy2DAsync(stage, dpitch, src + a * ld_sensor, spitch, dpitch, (size_t)Nt,
+                                        hipMemcpyHostToDevice, st));
+        } else {
+            for (int64_t i = 0; i < n; ++i)
+                BT_HIP(op, hipMemcpy2DAsync(stage + i * np, dpitch, src + (a + i) * ld_sensor, spitch,
+                                            (size_t)np * sizeof(double), (size_t)Nt, hipMemcpyHostToDevice, st));
+        }
+        const int64_t row = n * np;
+        BT_HIP(op, run(rev ? stage + (Nt - 1) * row : stage, rev ? -row : row, np, s0 + a, n));
+        BT_HIP(op, hipStreamSynchronize(st));
+    }
+    return BTOEP_OK;
+}
+
+// ---- persistence of the Fourier-space operator ----------------------------------------
+// File: a 64-byte little-endian header, then Fhat[f][s][p] (f <= N, s < Nd, p < Nm) in the
+// storage format (interleaved re, im).
+struct FileHeader {
+    char magic[8];  // "BTOEPFH\n"
+    uint32_t version, storage;
+    int64_t Nt, Nd, Nm, L;
+    uint64_t payload;
+    uint64_t reserved;
+};
+static_assert(sizeof(FileHeader) == 64, "operator file header is 64 bytes");
+constexpr char kMagic[8] = {'B', 'T', 'O', 'E', 'P', 'F', 'H', '\n'};
+constexpr size_t kFileChunk = (size_t)64 << 20;
+
+struct File {
+    FILE* f = nullptr;
+    ~File() {
+        if (f) fclose(f);
+    }
+};
+struct Pinned {
+    void* p = nullptr;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+btoep_status io_err(btoep_op op, const char* what, const char* path) {
+    snprintf(op ? op->err : g_err, 512, "%s: %s", what, path);
+    return BTOEP_ERR_IO;
+}
+
+btoep_status save_fhat(btoep_op op, const char* path, hipStream_t st) {
+    const size_t sb = stor_bytes(op->stor), row = (size_t)op->Nm * sb;
+    const int64_t rows = op->nfreq * op->Nd;
+    FileHeader h{};
+    memcpy(h.magic, kMagic, 8);
+    h.version = 1;
+    h.storage = (uint32_t)op->storage;
+    h.Nt = op->Nt;
+    h.Nd = op->Nd;
+    h.Nm = op->Nm;
+    h.L = op->L;
+    h.payload = (uint64_t)rows * row;
+    File fl;
+    fl.f = fopen(path, "wb");
+    if (!fl.f) return io_err(op, "cannot open for writing", path);
+    if (fwrite(&h, sizeof h, 1, fl.f) != 1) return io_err(op, "write failed", path);
+    const int64_t per = std::max<int64_t>(1, (int64_t)(kFileChunk / row));
+    Pinned buf;
+    BT_HIP(op, hipHostMalloc(&buf.p, (size_t)std::min<int64_t>(per, rows) * row, hipHostMallocDefault));
+    for (int64_t r0 = 0; r0 < rows; r0 += per) {
+        const int64_t n = std::min<int64_t>(per, rows - r0);
+        BT_HIP(op, hipMemcpy2DAsync(buf.p, row, (const char*)op->fhat + (size_t)r0 * op->ldF * sb, (size_t)op->ldF * sb,
+                                    row, (size_t)n, hipMemcpyDeviceToHost, st));
+        BT_HIP(op, hipStreamSynchronize(st));
+        if (fwrite(buf.p, row, (size_t)n, fl.f) != (size_t)n) return io_err(op, "write failed", path);
+    }
+    if (fflush(fl.f) != 0) return io_err(op, "write failed", path);
+    return BTOEP_OK;
+}
+
+// The header is checked against the file before any device work: magic, version, storage
+// code, sizes within the library's limits, the transform length the library derives from Nt,
+// and a payload of exactly the stated size.
+btoep_status load_fhat(const char* path, hipStream_t st, btoep_op* out) {
+    File fl;
+    fl.f = fopen(path, "rb");
+    if (!fl.f) return io_err(nullptr, "cannot open for reading", path);
+    FileHeader h{};
+    if (fread(&h, sizeof h, 1, fl.f) != 1) return io_err(nullptr, "truncated header", path);
+    if (memcmp(h.magic, kMagic, 8) != 0 || h.version != 1) return io_err(nullptr, "not an operator file", path);
+    if (h.storage > (uint32_t)BTOEP_BF16 || h.Nt < 1 || h.Nd < 1 || h.Nm < 1 || h.Nd > 65535 ||
+        h.Nm > ((int64_t)1 << 30) || h.Nt > ((int64_t)1 << 20) || h.L != 2 * choose_N(h.Nt))
+        return io_err(nullptr, "malformed operator header", path);
+    const size_t sb = h.storage == BTOEP_F64 ? 16 : (h.storage == BTOEP_F32 ? 8 : 4);
+    const size_t row = (size_t)h.Nm * sb;
+    const int64_t rows = (h.L / 2 + 1) * h.Nd;
+    if (h.payload != (uint64_t)rows * row) return io_err(nullptr, "malformed operator header", path);
+    if (fseeko(fl.f, 0, SEEK_END) != 0 || ftello(fl.f) != (off_t)(sizeof h + h.payload) ||
+        fseeko(fl.f, (off_t)sizeof h, SEEK_SET) != 0)
+        return io_err(nullptr, "file size does not match its header", path);
+
+    btoep_op op = nullptr;
+    btoep_status s = create_shell(h.Nt, h.Nd, h.Nm, (btoep_dtype)h.storage, false, st, &op);
+    if (s != BTOEP_OK) return s;
+    auto fail = [&](btoep_status e) {
+        snprintf(g_err, sizeof g_err, "%s", op->err);
+        btoep_destroy(op);
+        return e;
+    };
+    const int64_t per = std::max<int64_t>(1, (int64_t)(kFileChunk / row));
+    Pinned buf;
+    hipError_t e = hipHostMalloc(&buf.p, (size_t)std::min<int64_t>(per, rows) * row, hipHostMallocDefault);
+    for (int64_t r0 = 0; e == hipSuccess && r0 < rows; r0 += per) {
+        const int64_t n = std::min<int64_t>(per, rows - r0);
+        if (fread(buf.p, row, (size_t)n, fl.f) != (size_t)n) return fail(io_err(op, "read failed", path));
+        e = hipMemcpy2DAsync((char*)op->fhat + (size_t)r0 * op->ldF * sb, (size_t)op->ldF * sb, buf.p, row, row,
+                             (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) {
+        set_err(op, "operator load", e);
+        return fail(e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP);
+    }
     *out = op;
     return BTOEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* btoep_status_string(btoep_status s) {
+    switch (s) {
+        case BTOEP_OK: return "ok";
+        case BTOEP_ERR_INVALID_ARG: return "invalid argument";
+        case BTOEP_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case BTOEP_ERR_HIP: return "HIP runtime error";
+        case BTOEP_ERR_UNSUPPORTED: return "unsupported shape or option";
+        case BTOEP_ERR_NOT_CONVERGED: return "CG did not converge";
+        case BTOEP_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case BTOEP_ERR_IO: return "file I/O error or malformed operator file";
+    }
+    return "unknown status";
+}
+
+const char* btoep_last_error(btoep_op op) { return op ? op->err : g_err; }
+
+btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* blocks, btoep_memory where,
+                          btoep_dtype storage, void* stream, btoep_op* out) {
+    if (!out) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!blocks) return BTOEP_ERR_INVALID_ARG;
+    if (where != BTOEP_HOST && where != BTOEP_DEVICE) return BTOEP_ERR_INVALID_ARG;
+    btoep_op op = nullptr;
+    btoep_status s = create_shell(Nt, Nd, Nm, storage, false, (hipStream_t)stream, &op);
+    if (s != BTOEP_OK) return s;
+    s = fill_tile(op, 0, Nd, 0, Nm, blocks, Nd * Nm, Nm, BTOEP_BLOCK_COLUMN, where, (hipStream_t)stream);
+    if (s != BTOEP_OK) {
+        snprintf(g_err, sizeof g_err, "%s", op->err);
+        btoep_destroy(op);
+        return s;
+    }
+    *out = op;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_create_empty(int64_t Nt, int64_t Nd, int64_t Nm, btoep_dtype storage, void* stream,
+                                btoep_op* out) {
+    if (!out) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    return create_shell(Nt, Nd, Nm, storage, true, (hipStream_t)stream, out);
+}
+
+btoep_status btoep_set_blocks(btoep_op op, int64_t s0, int64_t ns, int64_t p0, int64_t np, const double* src,
+                              int64_t ld_time, int64_t ld_sensor, btoep_block_order order, btoep_memory where,
+                              void* stream) {
+    if (!op || !src) return BTOEP_ERR_INVALID_ARG;
+    if (order != BTOEP_BLOCK_COLUMN && order != BTOEP_LAST_BLOCK_ROW) return BTOEP_ERR_INVALID_ARG;
+    if (where != BTOEP_HOST && where != BTOEP_DEVICE) return BTOEP_ERR_INVALID_ARG;
+    if (s0 < 0 || ns < 1 || s0 + ns > op->Nd || p0 < 0 || np < 1 || p0 + np > op->Nm) return BTOEP_ERR_INVALID_ARG;
+    if (ld_sensor < np || (ns > 1 && ld_time < (ns - 1) * ld_sensor + np) || (ns == 1 && ld_time < np))
+        return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(op->device);
+    return fill_tile(op, s0, ns, p0, np, src, ld_time, ld_sensor, order, where, (hipStream_t)stream);
+}
+
+btoep_status btoep_save(btoep_op op, const char* path, void* stream) {
+    if (!op || !path) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(op->device);
+    return save_fhat(op, path, (hipStream_t)stream);
+}
+
+btoep_status btoep_load(const char* path, void* stream, btoep_op* out) {
+    if (!out) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!path) return BTOEP_ERR_INVALID_ARG;
+    return load_fhat(path, (hipStream_t)stream, out);
 }
 
 btoep_status btoep_destroy(btoep_op op) {

@@ -60,3 +60,63 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     g = ctypes.c_void_p()
     assert lib.btoep_graph_create(None, 2, 1, 1.0, 1.0, ctypes.c_void_p(8), 1 << 20, ctypes.byref(g)) == 1
     assert lib.btoep_graph_create(None, 2, 1, 1.0, 1.0, None, 0, None) == 1
+
+
+def test_setup_and_persistence_arguments_rejected(lib):
+    h = ctypes.c_void_p()
+    assert lib.btoep_create_empty(0, 1, 1, 1, None, ctypes.byref(h)) == 1
+    assert lib.btoep_create_empty(4, 1, 1, 9, None, ctypes.byref(h)) == 1
+    assert lib.btoep_create_empty(4, 1, 1, 1, None, None) == 1
+    assert lib.btoep_set_blocks(None, 0, 1, 0, 1, ctypes.c_void_p(1), 1, 1, 0, 0, None) == 1
+    assert lib.btoep_save(None, b"/tmp/x", None) == 1
+    assert lib.btoep_load(None, None, ctypes.byref(h)) == 1
+    assert lib.btoep_load(b"/tmp/x", None, None) == 1
+    assert "I/O" in lib.btoep_status_string(7).decode()
+
+
+def _header(Nt, Nd, Nm, storage=1, L=None, payload=None, magic=b"BTOEPFH\n", version=1):
+    import struct
+    N = Nt
+    while not _smooth(N):
+        N += 1
+    L = 2 * N if L is None else L
+    if payload is None:
+        payload = (L // 2 + 1) * Nd * Nm * {0: 16, 1: 8, 2: 4}[storage]
+    return struct.pack("<8sIIqqqqQQ", magic, version, storage, Nt, Nd, Nm, L, payload, 0), payload
+
+
+def _smooth(n):
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+@pytest.mark.parametrize("case", ["missing", "magic", "version", "length", "truncated", "long", "payload",
+                                  "storage", "short"])
+def test_malformed_operator_files_rejected_before_device_work(lib, tmp_path, case):
+    """btoep_load checks the whole header against the file on the host (status IO = 7)."""
+    path = tmp_path / "op.bin"
+    hdr, payload = _header(10, 2, 3)
+    body = b"\0" * payload
+    if case == "magic":
+        hdr, _ = _header(10, 2, 3, magic=b"BTOEPFX\n")
+    elif case == "version":
+        hdr, _ = _header(10, 2, 3, version=2)
+    elif case == "length":
+        hdr, _ = _header(10, 2, 3, L=24)  # the library pads Nt = 10 to N = 10, L = 20
+    elif case == "truncated":
+        body = body[:-1]
+    elif case == "long":
+        body = body + b"\0"
+    elif case == "payload":
+        hdr, _ = _header(10, 2, 3, payload=payload + 8)
+    elif case == "storage":
+        hdr, _ = _header(10, 2, 3, storage=5, payload=payload)
+    elif case == "short":
+        hdr, body = hdr[:40], b""
+    if case != "missing":
+        path.write_bytes(hdr + body)
+    h = ctypes.c_void_p()
+    assert lib.btoep_load(os.fsencode(str(path)), None, ctypes.byref(h)) == 7
+    assert not h.value
