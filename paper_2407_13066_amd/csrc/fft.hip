@@ -428,8 +428,10 @@ __device__ __forceinline__ void put(bf16c* p, cx<T> v) {
 }
 
 
-// Vector-side outputs are written with non-temporal stores: left as dirty lines in the
-// caches they would be written back while the next kernel streams the operator.
+// Vector-side outputs are written with non-temporal stores when a workgroup's run of P values
+// per row spans at least 64 bytes: left as dirty lines in the caches they would be written back
+// while the next kernel streams the operator.  Shorter runs (long series, narrow tiles) use
+// ordinary stores, which measured up to twice as fast for such partial lines.
 template <typename T>
 __device__ __forceinline__ void put_nt(cx<float>* p, cx<T> v) {
     typedef float f2v __attribute__((ext_vector_type(2)));
@@ -568,7 +570,7 @@ template <typename T, typename Tin, typename So, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_r2c(PtrBatch in, int64_t in_row, So* __restrict__ out,
                                                          int64_t out_row, int64_t out_batch, int Nt, int ncols,
                                                          FftPlan plan, int logP, const cx<T>* __restrict__ twg,
-                                                         int twl) {
+                                                         int twl, int ntw) {
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const int N = plan.N, P = 1 << logP;
     const int col0 = column_block() << logP;
@@ -582,9 +584,16 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     tile.commit(reinterpret_cast<T*>(fft_smem), Nt, N, logP, col0, ncols);
     __syncthreads();
     run_fft<T, -1, FftCfg<T>::CMAX, PL>(plan, logP, twl, tw_off, twg);
+#pragma unroll 4
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
-        if (col0 + c < ncols) put_nt(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
+        if (col0 + c < ncols) {
+            So* q = &y[(int64_t)f * out_row + col0 + c];
+            if (ntw)
+                put_nt(q, r2c_bin(sh, N, logP, f, c, tw));
+            else
+                put(q, r2c_bin(sh, N, logP, f, c, tw));
+        }
     }
 }
 
@@ -619,7 +628,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
                                                          int64_t in_batch, PtrBatch out, int64_t out_row,
                                                          PtrBatch add, T add_scale, int Nt, int ncols,
                                                          FftPlan plan, int logP, const cx<T>* __restrict__ twg,
-                                                         int twl, T out_scale) {
+                                                         int twl, T out_scale, int ntw) {
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const T* shr = reinterpret_cast<const T*>(fft_smem);
     const int N = plan.N, P = 1 << logP, P1 = P - 1;
@@ -665,7 +674,12 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
             const int c = e & P1, j = e >> logP;
             if (e < nout && col0 + c < ncols) {
                 const T v = out_scale * shr[2 * (((j >> 1) << logP) + c) + (j & 1)];
-                __builtin_nontemporal_store(a ? fma(add_scale, av[u], v) : v, &x[(int64_t)j * out_row + col0 + c]);
+                T* q = &x[(int64_t)j * out_row + col0 + c];
+                const T w = a ? fma(add_scale, av[u], v) : v;
+                if (ntw)
+                    __builtin_nontemporal_store(w, q);
+                else
+                    *q = w;
             }
         }
     }
@@ -716,12 +730,10 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 static size_t elem_of(Real r) { return r == Real::F64 ? 16 : 8; }
 static int cmax_of(Real r) { return r == Real::F64 ? FftCfg<double>::CMAX : FftCfg<float>::CMAX; }
 
-// Twiddles live in LDS whenever one column plus the table fits.
-static bool twl_of(int N, Real r) { return (size_t)(N + 1 + 2 * N) * elem_of(r) <= kFftLdsBudget; }
-
-int fft_log_cols(int N, Real r) {
+// Widest column tile (log2) of a length-N transform, with or without the twiddle table in LDS.
+static int max_log_cols(int N, Real r, bool twl) {
     const size_t elem = elem_of(r);
-    const size_t tw = twl_of(N, r) ? (size_t)2 * N * elem : 0;
+    const size_t tw = twl ? (size_t)2 * N * elem : 0;
     for (int lp = 6; lp >= 0; --lp) {
         const size_t P = (size_t)1 << lp;
         if ((size_t)(N + 1) * P * elem + tw <= kFftLdsBudget && (size_t)N * P <= (size_t)cmax_of(r) * kFftThreads)
@@ -729,6 +741,16 @@ int fft_log_cols(int N, Real r) {
     }
     return -1;
 }
+
+// Twiddles live in LDS when they fit without narrowing the column tile: every global access
+// of a tile is a run of P consecutive columns, and runs shorter than a cache line cost more
+// than twiddle reads from the caches.
+static bool twl_of(int N, Real r) {
+    const int with = max_log_cols(N, r, true);
+    return with >= 0 && with >= max_log_cols(N, r, false);
+}
+
+int fft_log_cols(int N, Real r) { return max_log_cols(N, r, twl_of(N, r)); }
 
 size_t fft_lds_bytes(int N, int logP, Real r) {
     const size_t elem = elem_of(r);
@@ -806,7 +828,7 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
 #define BT_R2C(PLAN)                                                                                       \
     k_fft_r2c<float, float, cx<float>, PLAN><<<grid, block, lds, st>>>(in, in_row, (cx<float>*)out, out_row, \
                                                                        out_batch, Nt, ncols, plan, lp,      \
-                                                                       (const cx<float>*)tw, twl)
+                                                                       (const cx<float>*)tw, twl, (8 << lp) >= 64)
         switch (static_plan_id(plan, r)) {
 #define BT_CASE(ID, PLAN) \
     case ID: BT_R2C(PLAN); break;
@@ -817,7 +839,7 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
 #undef BT_R2C
     } else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128) {
         k_fft_r2c<double, double, cx<double>, RuntimePlan><<<grid, block, lds, st>>>(
-            in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, plan, lp, (const cx<double>*)tw, twl);
+            in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, plan, lp, (const cx<double>*)tw, twl, 0);
     } else {
         return hipErrorInvalidValue;
     }
@@ -864,7 +886,7 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
 #define BT_C2R(PLAN)                                                                                            \
     k_fft_c2r<float, PLAN><<<grid, block, lds, st>>>((const cx<float>*)in, in_row, in_batch, out, out_row, add, \
                                                      (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw, \
-                                                     twl, (float)out_scale)
+                                                     twl, (float)out_scale, (4 << lp) >= 64)
         switch (static_plan_id(plan, r)) {
 #define BT_CASE(ID, PLAN) \
     case ID: BT_C2R(PLAN); break;
@@ -876,7 +898,8 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
     } else {
         k_fft_c2r<double, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out,
                                                                  out_row, add, add_scale, Nt, ncols, plan, lp,
-                                                                 (const cx<double>*)tw, twl, out_scale);
+                                                                 (const cx<double>*)tw, twl, out_scale,
+                                                                 (8 << lp) >= 64);
     }
     return hipGetLastError();
 }
