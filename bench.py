@@ -323,6 +323,49 @@ def paper_shapes_benchmark(bt):
     return out
 
 
+def appendix_benchmark(bt):
+    """The paper's appendix comparison in FP64: its alternate local matvec (SOTI products, then
+    sums over block rows / columns) against the frequency-outer products, at the two shapes the
+    appendix reports (Nt=2000 with Nd=7, Nm=40000 and with Nd=100, Nm=4000).  Mode 0 writes the
+    products to a matrix-sized buffer and reduces them in a second kernel, as the appendix does;
+    mode 1 forms them inside the reduction."""
+    import torch
+    import synth
+    out = []
+    for Nt, Nd, Nm in ((2000, 7, 40000), (2000, 100, 4000)):
+        blocks = synth.blocks(Nt, Nd, Nm, Nt / 7.0, stream=21)
+        op = bt.btoep_create(blocks, "f64")
+        del blocks
+        bt.btoep_autotune(op, reps=3)
+        m = torch.randn((Nt, Nm), dtype=torch.float64, device="cuda")
+        d = torch.randn((Nt, Nd), dtype=torch.float64, device="cuda")
+
+        def per_call(fn, reps=10):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3 / reps
+
+        res = {"Nt": Nt, "Nd": Nd, "Nm": Nm, "storage": "c128",
+               "main_F_ms": round(per_call(lambda: bt.btoep_apply_F(op, m)), 3),
+               "main_FT_ms": round(per_call(lambda: bt.btoep_apply_FT(op, d)), 3)}
+        for mode in (1, 0):
+            bt.btoep_alt_prepare(op, mode)
+            res["alt%d_F_ms" % mode] = round(per_call(lambda: bt.btoep_alt_apply(op, "F", m, mode=mode)), 3)
+            res["alt%d_FT_ms" % mode] = round(per_call(lambda: bt.btoep_alt_apply(op, "FT", d, mode=mode)), 3)
+        log("appendix form Nt=%d Nd=%d Nm=%d FP64: F main %.3f / fused %.3f / two-kernel %.3f ms; "
+            "F^T %.3f / %.3f / %.3f ms" % (Nt, Nd, Nm, res["main_F_ms"], res["alt1_F_ms"], res["alt0_F_ms"],
+                                            res["main_FT_ms"], res["alt1_FT_ms"], res["alt0_FT_ms"]))
+        out.append(res)
+        op.destroy()
+        del m, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def setup_benchmark(bt, blocks, storage, host_s):
     """Setup of the stored operator (transform of every block series, Alg. 1 on one device) from
     device-resident FP64 blocks, given as the first block column and as the last block row; the
@@ -421,6 +464,8 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solve measurement")
     ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape (FP64) context runs")
     ap.add_argument("--no-setup", action="store_true", help="skip the setup (block transform) measurement")
+    ap.add_argument("--no-appendix", action="store_true",
+                    help="skip the comparison with the paper's appendix (SOTI) matvec form")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
                     help="parameter columns of the operator the CPU oracle is timed on")
     args = ap.parse_args()
@@ -612,6 +657,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_paper_shapes:
         result["paper_shapes"] = paper_shapes_benchmark(bt)
+        torch.cuda.empty_cache()
+    if not args.no_appendix:
+        result["appendix_form"] = appendix_benchmark(bt)
         torch.cuda.empty_cache()
     if args.serving_requests > 0:
         result["serving"] = serving_benchmark(bt, args.serving_requests, rates=(0.5, 0.9))

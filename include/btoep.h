@@ -136,6 +136,26 @@ btoep_status btoep_set_blocks(btoep_op op, int64_t s0, int64_t ns, int64_t p0, i
 btoep_status btoep_save(btoep_op op, const char* path, void* stream);
 btoep_status btoep_load(const char* path, void* stream, btoep_op* out);
 
+/*
+ * For comparison only: the paper's alternate local matvec (appendix).  The transformed
+ * blocks are kept a second time in SOTI order, Fs[s][p][f] (every sensor-parameter series
+ * contiguous over frequency), and the frequency-domain step becomes elementwise products with
+ * the vector spectrum in SOTI order followed by sums over block rows (F) or block columns (F^T):
+ *     dhat[s][f] = sum_p Fs[s][p][f] mhat[p][f],   mhat'[p][f] = sum_s conj(Fs[s][p][f]) dhat[s][f].
+ * mode 0 follows the appendix (products written to a matrix-sized buffer, then a separate
+ * reduction); mode 1 forms the products inside the reduction.  Transforms and time-domain
+ * steps are those of btoep_apply_F / btoep_apply_FT, with transposes between the orderings.
+ * btoep_alt_prepare allocates the SOTI copy (the stored operator's size again) and, for mode 0,
+ * the product buffer (the same size in the vector precision), fills the copy from the stored
+ * operator and returns when done.  btoep_alt_apply applies F (which = BTOEP_APPLY_F: m [Nt][Nm]
+ * -> d [Nt][Nd]) or F^T (BTOEP_APPLY_FT: d -> m) to one right-hand side, using the operator's
+ * own workspace; call btoep_alt_prepare with the same mode first.
+ * Errors: INVALID_ARG (bad enums, null pointers, not prepared), UNSUPPORTED (more than about
+ * 2^21 frequencies or parameters, or Nd Nm >= 2^31), OUT_OF_MEMORY, HIP.
+ */
+btoep_status btoep_alt_prepare(btoep_op op, int mode, void* stream);
+btoep_status btoep_alt_apply(btoep_op op, btoep_which which, int mode, const void* in, void* out, void* stream);
+
 /* Releases the operator and everything it owns (synchronises its device). */
 btoep_status btoep_destroy(btoep_op op);
 

@@ -79,6 +79,8 @@ def load_library(path=LIB_PATH):
         "btoep_set_blocks": ([vp, i64, i64, i64, i64, vp, i64, i64, ctypes.c_int, ctypes.c_int, vp], st),
         "btoep_save": ([vp, ctypes.c_char_p, vp], st),
         "btoep_load": ([ctypes.c_char_p, vp, ctypes.POINTER(vp)], st),
+        "btoep_alt_prepare": ([vp, ctypes.c_int, vp], st),
+        "btoep_alt_apply": ([vp, ctypes.c_int, ctypes.c_int, vp, vp, vp], st),
         "btoep_destroy": ([vp], st),
         "btoep_query": ([vp, ctypes.POINTER(_Info)], st),
         "btoep_workspace_size": ([vp, ctypes.c_int, i64, ctypes.POINTER(sz)], st),
@@ -245,6 +247,32 @@ def btoep_load(path, stream=None):
     h = ctypes.c_void_p()
     _check(load_library().btoep_load(os.fsencode(path), _stream(stream), ctypes.byref(h)), "btoep_load")
     return Op(h, btoep_query(h))
+
+
+def btoep_alt_prepare(op, mode=1, stream=None):
+    """Build the SOTI copy of the stored operator for the appendix form (mode 0: products then
+    a separate reduction, as in the paper's appendix; mode 1: fused)."""
+    _check(load_library().btoep_alt_prepare(op.handle, int(mode), _stream(stream)), "btoep_alt_prepare", op.handle)
+
+
+def btoep_alt_apply(op, which, x, mode=1, out=None, stream=None):
+    """F (which "F": x = m [Nt][Nm]) or F^T ("FT": x = d [Nt][Nd]) by the appendix form; one
+    right-hand side.  For comparison with btoep_apply_F / btoep_apply_FT."""
+    torch = _torch()
+    if which not in ("F", "FT"):
+        raise ValueError("which must be 'F' or 'FT'")
+    tin = (op.Nt, op.Nm) if which == "F" else (op.Nt, op.Nd)
+    tout = (op.Nt, op.Nd) if which == "F" else (op.Nt, op.Nm)
+    if not x.is_cuda or x.dtype != op.vector_dtype or not x.is_contiguous() or tuple(x.shape) != tin:
+        raise ValueError("input must be a contiguous %s CUDA tensor of shape %s" % (op.vector_dtype, list(tin)))
+    if out is None:
+        out = torch.empty(tout, dtype=x.dtype, device=x.device)
+    if not out.is_cuda or out.dtype != x.dtype or not out.is_contiguous() or tuple(out.shape) != tout:
+        raise ValueError("out must be a contiguous %s CUDA tensor of shape %s" % (x.dtype, list(tout)))
+    _check(load_library().btoep_alt_apply(op.handle, WHICH[which], int(mode), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+           "btoep_alt_apply", op.handle)
+    return out
 
 
 def btoep_destroy(op):

@@ -37,6 +37,16 @@ struct btoep_op_s {
     void* ltw2_32 = nullptr;
     bool gemm_enabled = true;  // MFMA kernels for several right-hand sides
     int var_n = 3, var_c = 3;  // single-vector kernel variants (see sbgemv_variants)
+    // the appendix (SOTI) form, kept for comparison: Fs[s][p][f] with rows of alt_ldf, the
+    // matrix-sized product buffer, SOTI vector spectra and partial sums over parameter chunks
+    bool alt_ready = false;
+    void* alt_fs = nullptr;
+    void* alt_q = nullptr;
+    void* alt_v = nullptr;
+    void* alt_d = nullptr;
+    void* alt_part = nullptr;
+    int64_t alt_ldf = 0;
+    int alt_chunk = 0, alt_nchunk = 0;
     void* ws = nullptr;    // operator-owned workspace (used when the caller passes none)
     size_t ws_cap = 0;
     std::mutex mu;
@@ -842,7 +852,8 @@ btoep_status btoep_destroy(btoep_op op) {
     if (op->fhat) (void)hipFree(op->fhat);
     if (op->tw64) (void)hipFree(op->tw64);
     if (op->tw32) (void)hipFree(op->tw32);
-    for (void* q : {op->ltw1_64, op->ltw2_64, op->ltw1_32, op->ltw2_32})
+    for (void* q : {op->ltw1_64, op->ltw2_64, op->ltw1_32, op->ltw2_32, op->alt_fs, op->alt_q, op->alt_v, op->alt_d,
+                    op->alt_part})
         if (q) (void)hipFree(q);
     if (op->ws) (void)hipFree(op->ws);
     for (auto& p : op->pending) {
@@ -1255,6 +1266,93 @@ btoep_status btoep_set_fft(btoep_op op, int64_t n1) {
     const btoep_status s = set_long(op, n1 == 0 ? (fft_log_cols((int)op->N, Real::F64) < 0 ? 0 : -1) : n1);
     if (s != BTOEP_OK && n1 != 0) (void)set_long(op, fft_log_cols((int)op->N, Real::F64) < 0 ? 0 : -1);
     return s;
+}
+
+btoep_status btoep_alt_prepare(btoep_op op, int mode, void* stream) {
+    if (!op || (mode != 0 && mode != 1)) return BTOEP_ERR_INVALID_ARG;
+    const int64_t nf = op->nfreq, Nd = op->Nd, Nm = op->Nm;
+    if (nf > 65535LL * 32 || Nm > 65535LL * 32 || Nd * Nm > 2147483647LL) return BTOEP_ERR_UNSUPPORTED;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t sb = stor_bytes(op->stor), vc = 2 * vbytes(op);
+    if (!op->alt_ready) {
+        const int64_t ldf = (int64_t)align_up((size_t)nf, 8);
+        // parameter chunks of the sums over p: enough (chunk, frequency block, sensor)
+        // workgroups to fill the chip
+        const int64_t fb = (nf + 255) / 256;
+        int64_t nchunk = std::min<int64_t>(std::min<int64_t>(Nm, 65535), std::max<int64_t>(1, 4096 / (fb * Nd)));
+        const int64_t chunk = (Nm + nchunk - 1) / nchunk;
+        nchunk = (Nm + chunk - 1) / chunk;
+        if (!op->alt_fs) BT_HIP(op, hipMalloc(&op->alt_fs, (size_t)Nd * Nm * ldf * sb));
+        if (!op->alt_v) BT_HIP(op, hipMalloc(&op->alt_v, (size_t)Nm * ldf * vc));
+        if (!op->alt_d) BT_HIP(op, hipMalloc(&op->alt_d, (size_t)Nd * ldf * vc));
+        if (!op->alt_part) BT_HIP(op, hipMalloc(&op->alt_part, (size_t)Nd * nf * nchunk * vc));
+        op->alt_ldf = ldf;
+        op->alt_chunk = (int)chunk;
+        op->alt_nchunk = (int)nchunk;
+        // Fhat[f][s][p] -> Fs[s][p][f], one sensor per batch
+        BT_HIP(op, launch_transpose(sb, op->fhat, Nd * op->ldF, op->ldF, op->alt_fs, ldf, Nm * ldf, (int)nf, (int)Nm,
+                                    (int)Nd, st));
+        BT_HIP(op, hipStreamSynchronize(st));
+        op->alt_ready = true;
+    }
+    if (mode == 0 && !op->alt_q) BT_HIP(op, hipMalloc(&op->alt_q, (size_t)Nd * Nm * op->alt_ldf * vc));
+    return BTOEP_OK;
+}
+
+btoep_status btoep_alt_apply(btoep_op op, btoep_which which, int mode, const void* in, void* out, void* stream) {
+    if (!op || !in || !out || (which != BTOEP_APPLY_F && which != BTOEP_APPLY_FT) || (mode != 0 && mode != 1))
+        return BTOEP_ERR_INVALID_ARG;
+    if (!op->alt_ready || (mode == 0 && !op->alt_q)) return BTOEP_ERR_INVALID_ARG;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    const ApplyWs w = apply_layout(op, BTOEP_APPLY_H, 1);
+    btoep_status s = get_ws(op, w.total, ws, ws_bytes);
+    if (s != BTOEP_OK) return s;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    void* vh = base + w.vh;
+    void* dh = base + w.dh;
+    void* tmp = base + w.tmp;
+    void* spec = base + w.spec;
+    const int Nt = (int)op->Nt, Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
+    const int64_t N = op->N, ldf = op->alt_ldf;
+    const size_t vc = 2 * vbytes(op);
+    const Real vr = op->vreal;
+    const void* tw = tw_of(op);
+    const void* tw1 = vr == Real::F64 ? op->ltw1_64 : op->ltw1_32;
+    const void* tw2 = vr == Real::F64 ? op->ltw2_64 : op->ltw2_32;
+    const bool fused = mode == 1;
+    PtrBatch pi{}, po{}, none{};
+    pi.p[0] = in;
+    po.p[0] = out;
+    if (which == BTOEP_APPLY_F) {
+        BT_HIP(op, vec_r2c(op, 1, pi, vh, tmp, st));
+        BT_HIP(op, launch_transpose(vc, vh, op->ldv, 0, op->alt_v, ldf, 0, nf, Nm, 1, st));
+        BT_HIP(op, launch_alt_product(op->stor, vr, false, fused, op->alt_fs, op->alt_v, op->alt_part, op->alt_q, Nd,
+                                      Nm, nf, ldf, op->alt_chunk, op->alt_nchunk, st));
+        const double inv_n = 1.0 / (double)N;
+        if (!op->fft_long) {
+            BT_HIP(op, launch_dside(vr, op->alt_part, op->alt_nchunk, 0, 1, &po, nullptr, 0, Nt, Nd, op->plan, tw, inv_n,
+                                    st));
+        } else {
+            BT_HIP(op, launch_sum_spans(vr, op->alt_part, op->alt_nchunk, 0, spec, (int64_t)nf * Nd, nf, Nd, 1, st));
+            BT_HIP(op, launch_long_c2r(vr, spec, Nd, (int64_t)nf * Nd, 1, tmp, Nd, N * Nd, po, Nd, none, 0.0, Nt, Nd,
+                                       op->lp1, op->lp2, tw1, tw2, tw, inv_n, st));
+        }
+        return BTOEP_OK;
+    }
+    BT_HIP(op, op->fft_long ? launch_long_r2c(vr, vr, vstor(op), pi, 0, Nd, 1, Nt, Nd, tmp, Nd, N * Nd, dh, Nd,
+                                              (int64_t)nf * Nd, op->lp1, op->lp2, tw1, tw2, tw, st)
+                            : launch_fft_r2c(vr, vr, vstor(op), pi, Nd, 1, dh, Nd, (int64_t)nf * Nd, Nt, Nd, op->plan,
+                                             tw, st));
+    BT_HIP(op, launch_transpose(vc, dh, Nd, 0, op->alt_d, ldf, 0, nf, Nd, 1, st));
+    BT_HIP(op, launch_alt_product(op->stor, vr, true, fused, op->alt_fs, op->alt_d, op->alt_v, op->alt_q, Nd, Nm, nf,
+                                  ldf, op->alt_chunk, op->alt_nchunk, st));
+    BT_HIP(op, launch_transpose(vc, op->alt_v, ldf, 0, vh, op->ldv, 0, Nm, nf, 1, st));
+    BT_HIP(op, vec_c2r(op, 1, vh, tmp, po, none, 0.0, st));
+    return BTOEP_OK;
 }
 
 btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma) {

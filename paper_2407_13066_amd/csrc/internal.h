@@ -61,6 +61,17 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
                         const PtrBatch* dout, void* dh, int64_t dh_batch, int Nt, int Nd,
                         const FftPlan& plan, const void* tw, double scale, hipStream_t st);
 
+// ---- the appendix (SOTI) form of the frequency-domain step (alt.hip) --------------------
+// out[b][c][r] = in[b][r][c] (r < rows, c < cols) for elements of `elem` bytes (16, 8 or 4).
+hipError_t launch_transpose(size_t elem, const void* in, int64_t in_ld, int64_t in_batch, void* out, int64_t out_ld,
+                            int64_t out_batch, int rows, int cols, int nb, hipStream_t st);
+// F (adj false): vout = part[s][f][c], the sums over parameter chunk c (chunk columns each) of
+// Fs[s][p][f] * vin[p][f]; F^T (adj true): vout[p][f] = sum_s conj(Fs[s][p][f]) vin[s][f].
+// Rows of Fs, vin and vout (SOTI) have stride ldf.  Unfused, the products go through the
+// matrix-sized buffer Q[s][p][f] first.  Compute precision r, operator storage os.
+hipError_t launch_alt_product(Stor os, Real r, bool adj, bool fused, const void* Fs, const void* vin, void* vout,
+                              void* Q, int Nd, int Nm, int nf, int64_t ldf, int chunk, int nchunk, hipStream_t st);
+
 // ---- four-step transforms for long series (fft.hip) ------------------------------------
 // N = N1 N2 (plans p1, p2; sub-twiddle tables tw1, tw2 of exp(-2 pi i t / (2 Nsub)), t < 2 Nsub;
 // twN the operator's table).  Same inputs and outputs as launch_fft_r2c / launch_fft_c2r plus

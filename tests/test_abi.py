@@ -120,3 +120,8 @@ def test_malformed_operator_files_rejected_before_device_work(lib, tmp_path, cas
     h = ctypes.c_void_p()
     assert lib.btoep_load(os.fsencode(str(path)), None, ctypes.byref(h)) == 7
     assert not h.value
+
+
+def test_alt_form_arguments_rejected(lib):
+    assert lib.btoep_alt_prepare(None, 1, None) == 1
+    assert lib.btoep_alt_apply(None, 0, 1, None, None, None) == 1
