@@ -76,19 +76,36 @@ def blas_threads():
 
 
 def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, check_cols=1):
-    """H applies with k stacked right-hand sides on the FP32- and BF16-stored operator
-    (matrix-core products); per-right-hand-side time against the single-vector H, matrix-core
-    throughput of the products, and the error of sampled columns against the FP64 oracle."""
+    """H applies with k stacked right-hand sides on the FP32-, BF16- and FP64-stored operator
+    (matrix-core products); per-right-hand-side time against the single-vector H of the same
+    storage, matrix-core throughput of the products, and the error of sampled columns against
+    the FP64 oracle."""
     import torch
     import oracle
     import synth
     Nt, Nd, Nm = blocks.shape
     out = {}
-    for storage in ("f32", "bf16"):
-        op = op32 if storage == "f32" else bt.btoep_create(blocks, "bf16")
+    for storage in ("f32", "bf16", "f64"):
+        op = op32 if storage == "f32" else bt.btoep_create(blocks, storage)
+        vn = np.float64 if storage == "f64" else np.float32
         res = {}
+        h1 = h1_ms
+        if storage == "f64":
+            # the single-vector FP64 H this storage is compared with
+            bt.btoep_autotune(op, reps=3)
+            m1 = torch.from_numpy(synth.vectors(1, Nt, Nm, synth.STREAM_M)).cuda()
+            bt.btoep_apply_H(op, m1, 1.0, 1.0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                bt.btoep_apply_H(op, m1, 1.0, 1.0)
+            torch.cuda.synchronize()
+            h1 = (time.perf_counter() - t) * 1e3 / 5
+            res["k1"] = {"ms": round(h1, 3)}
+            log("FP64 storage k=1: %.2f ms per H" % h1)
+            del m1
         for k in ks:
-            M = torch.from_numpy(synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=np.float32)).cuda()
+            M = torch.from_numpy(synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=vn)).cuda()
             HM = torch.empty_like(M)
             ws = torch.empty(bt.btoep_workspace_size(op, "H", k), dtype=torch.uint8, device="cuda")
             bt.btoep_apply_H(op, M, 1.0, 1.0, out=HM, ws=ws)
@@ -116,9 +133,9 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, check_cols=1):
                 got = HM[:check_cols].double().cpu().numpy()
                 errs = [oracle.rel_l2(got[r], ref[r]) for r in range(check_cols)]
             res["k%d" % k] = {"ms": round(ms, 3), "ms_per_rhs": round(ms / k, 4),
-                              "gain_vs_k1": round(h1_ms / (ms / k), 2), "products": kern,
+                              "gain_vs_k1": round(h1 / (ms / k), 2), "products": kern,
                               **({"rel_err_sampled": errs} if errs else {})}
-            log("multi-RHS %s k=%d: %.2f ms (%.3f ms/RHS, x%.1f vs k=1)" % (storage, k, ms, ms / k, h1_ms / (ms / k)))
+            log("multi-RHS %s k=%d: %.2f ms (%.3f ms/RHS, x%.1f vs k=1)" % (storage, k, ms, ms / k, h1 / (ms / k)))
             del M, HM, ws
             torch.cuda.empty_cache()
         out[storage] = res

@@ -296,7 +296,7 @@ Stor vstor(const btoep_op op) { return op->vreal == Real::F64 ? Stor::C128 : Sto
 
 // Per-frequency products: one vector per launch row (GEMV kernels) for a single right-hand
 // side or FP64 storage; the MFMA kernels for nb >= 2 on FP32 / BF16 storage.
-bool use_gemm(const btoep_op op, int nb) { return nb >= 2 && op->stor != Stor::C128 && op->gemm_enabled; }
+bool use_gemm(const btoep_op op, int nb) { return nb >= 2 && op->gemm_enabled; }
 
 hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part, int nspan, int64_t part_b,
                   hipStream_t st) {
@@ -306,11 +306,16 @@ hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part,
         // and runs on the matrix cores
         const int ng = (nb + kGemmNMax - 1) / kGemmNMax;
         const int g = (nb + ng - 1) / ng;
+        const size_t cb = 2 * vbytes(op);  // bytes of a vector-side complex value
         for (int r0 = 0; r0 < nb; r0 += g) {
             const int n = std::min(g, nb - r0);
-            hipError_t e = launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
-                                           (const char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, n,
-                                           (char*)part + (size_t)r0 * part_b * 8, nspan, part_b, st);
+            const void* v = (const char*)vh + (size_t)r0 * vh_b * cb;
+            void* pt = (char*)part + (size_t)r0 * part_b * cb;
+            hipError_t e = op->stor == Stor::C128
+                               ? launch_sbgemm_n64(op->fhat, op->ldF, nf, Nd, Nm, v, op->ldv, vh_b, n, pt, nspan,
+                                                   part_b, st)
+                               : launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, v, op->ldv, vh_b, n, pt,
+                                                 nspan, part_b, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -323,17 +328,22 @@ hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, i
     const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
     if (use_gemm(op, nb)) {
         // right-hand-side groups small enough for the staged data spectra
-        int g = nb;
-        while (g > 1 && sbgemm_c_lds(g, Nd) > 64 * 1024) g = (g + 1) / 2;
+        const bool f64 = op->stor == Stor::C128;
+        const size_t cb = 2 * vbytes(op);  // bytes of a vector-side complex value
+        int g = f64 ? std::min(nb, kGemmNMax) : nb;
+        while (g > 1 && (f64 ? sbgemm_c64_lds(g, Nd) : sbgemm_c_lds(g, Nd)) > 64 * 1024) g = (g + 1) / 2;
         for (int r0 = 0; r0 < nb; r0 += g) {
             const int n = std::min(g, nb - r0);
-            hipError_t e = (n >= 2) ? launch_sbgemm_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
-                                                      (const char*)dh + (size_t)r0 * dh_b * 8, dh_b, n,
-                                                      (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st)
-                                    : launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm,
-                                                      (const char*)dh + (size_t)r0 * dh_b * 8, dh_b, n,
-                                                      (char*)vh + (size_t)r0 * vh_b * 8, op->ldv, vh_b, st,
-                                                      op->var_c);
+            const void* d = (const char*)dh + (size_t)r0 * dh_b * cb;
+            void* o = (char*)vh + (size_t)r0 * vh_b * cb;
+            hipError_t e;
+            if (n < 2)
+                e = launch_sbgemv_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st,
+                                    op->var_c);
+            else if (f64)
+                e = launch_sbgemm_c64(op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st);
+            else
+                e = launch_sbgemm_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

@@ -61,6 +61,15 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
                         const PtrBatch* dout, void* dh, int64_t dh_batch, int Nt, int Nd,
                         const FftPlan& plan, const void* tw, double scale, hipStream_t st);
 
+// ---- launchers (sbgemm64.hip): the same for the complex FP64 operator ------------------
+// FP64 operands and accumulation on the FP64 matrix cores; at most kGemmNMax right-hand
+// sides per launch; sbgemm_c64 needs sbgemm_c64_lds(nb, Nd) <= 64 KB.
+size_t sbgemm_c64_lds(int nb, int Nd);
+hipError_t launch_sbgemm_n64(const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh, int64_t ldv,
+                             int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch, hipStream_t s);
+hipError_t launch_sbgemm_c64(const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* dh,
+                             int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s);
+
 // ---- the appendix (SOTI) form of the frequency-domain step (alt.hip) --------------------
 // out[b][c][r] = in[b][r][c] (r < rows, c < cols) for elements of `elem` bytes (16, 8 or 4).
 hipError_t launch_transpose(size_t elem, const void* in, int64_t in_ld, int64_t in_batch, void* out, int64_t out_ld,
