@@ -85,7 +85,8 @@ typedef struct {
  *   out    : receives the new operator (owned by the caller; free with btoep_destroy).
  * Uses the current HIP device.  Series too long for one workgroup's local memory use the
  * four-step transforms (see btoep_set_fft).  Errors: INVALID_ARG (sizes < 1, null pointers),
- * UNSUPPORTED (Nt > 2^20, Nd > 65535, Nm > 2^30), OUT_OF_MEMORY, HIP.
+ * UNSUPPORTED (Nt > 64827, i.e. more than 65535 stored frequencies; Nd > 65535; Nm > 2^30),
+ * OUT_OF_MEMORY, HIP.
  */
 btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* blocks, btoep_memory where,
                           btoep_dtype storage, void* stream, btoep_op* out);

@@ -100,6 +100,11 @@ bool is_7smooth(int64_t n) {
 
 // Smallest 7-smooth N >= Nt: any padded length L = 2N >= 2Nt - 1 gives the exact linear
 // convolution; 2N keeps the even/odd real-transform packing.
+// Stored frequencies are a grid dimension of the product kernels (at most 65535), which bounds
+// the series length: N + 1 <= 65535, i.e. Nt <= 64827 = 3^3 7^4 (the largest 7-smooth N
+// below 65535).
+constexpr int64_t kMaxFreq = 65535;
+
 int64_t choose_N(int64_t Nt) {
     int64_t n = std::max<int64_t>(Nt, 1);
     while (!is_7smooth(n)) ++n;
@@ -528,10 +533,10 @@ btoep_status create_shell(int64_t Nt, int64_t Nd, int64_t Nm, btoep_dtype storag
     *out = nullptr;
     if (Nt < 1 || Nd < 1 || Nm < 1) return BTOEP_ERR_INVALID_ARG;
     if (storage != BTOEP_F64 && storage != BTOEP_F32 && storage != BTOEP_BF16) return BTOEP_ERR_INVALID_ARG;
-    if (Nd > 65535 || Nm > ((int64_t)1 << 30) || Nt > ((int64_t)1 << 20)) return BTOEP_ERR_UNSUPPORTED;
+    if (Nd > 65535 || Nm > ((int64_t)1 << 30) || Nt > kMaxFreq) return BTOEP_ERR_UNSUPPORTED;
     const int64_t N = choose_N(Nt);
     FftPlan plan;
-    if (!make_plan(N, plan)) return BTOEP_ERR_UNSUPPORTED;
+    if (N + 1 > kMaxFreq || !make_plan(N, plan)) return BTOEP_ERR_UNSUPPORTED;
 
     btoep_op op = new (std::nothrow) btoep_op_s();
     if (!op) return BTOEP_ERR_OUT_OF_MEMORY;
@@ -747,7 +752,7 @@ btoep_status load_fhat(const char* path, hipStream_t st, btoep_op* out) {
     if (fread(&h, sizeof h, 1, fl.f) != 1) return io_err(nullptr, "truncated header", path);
     if (memcmp(h.magic, kMagic, 8) != 0 || h.version != 1) return io_err(nullptr, "not an operator file", path);
     if (h.storage > (uint32_t)BTOEP_BF16 || h.Nt < 1 || h.Nd < 1 || h.Nm < 1 || h.Nd > 65535 ||
-        h.Nm > ((int64_t)1 << 30) || h.Nt > ((int64_t)1 << 20) || h.L != 2 * choose_N(h.Nt))
+        h.Nm > ((int64_t)1 << 30) || h.Nt > kMaxFreq || h.L != 2 * choose_N(h.Nt) || h.L / 2 + 1 > kMaxFreq)
         return io_err(nullptr, "malformed operator header", path);
     const size_t sb = h.storage == BTOEP_F64 ? 16 : (h.storage == BTOEP_F32 ? 8 : 4);
     const size_t row = (size_t)h.Nm * sb;

@@ -198,19 +198,29 @@ def test_query_and_workspace(bt):
         bt.btoep_apply_F(op, torch.zeros((420, 17), dtype=torch.float32, device="cuda"), ws=ws)
 
 
-def test_long_series_supported_and_overlong_refused(bt):
-    """Nt = 5000 does not fit one workgroup in FP64 (four-step transforms take over); beyond
-    2^20 steps create refuses."""
+@pytest.mark.parametrize("Nt", [5000, 64827])
+def test_long_series_supported_and_overlong_refused(bt, Nt):
+    """Nt = 5000 does not fit one workgroup in FP64 (four-step transforms take over); Nt = 64827
+    is the longest series (65535 stored frequencies, the products' grid limit), checked against
+    np.convolve for F and np.correlate for F^T; one step more and create refuses."""
     rng = np.random.default_rng(9)
-    blocks = rng.standard_normal((5000, 1, 1)) * np.exp(-np.arange(5000) / 700.0)[:, None, None]
-    m = rng.standard_normal((5000, 1))
+    blocks = rng.standard_normal((Nt, 1, 1)) * np.exp(-np.arange(Nt) / (Nt / 7.0))[:, None, None]
+    m = rng.standard_normal((Nt, 1))
+    print("long series", Nt, flush=True)
     op = bt.btoep_create(blocks, "f64")
+    assert op.info["nfreq"] <= 65535
     d = bt.btoep_apply_F(op, to_dev(m, torch.float64))
+    mt = bt.btoep_apply_FT(op, to_dev(m, torch.float64))
     torch.cuda.synchronize()
-    ref = np.convolve(blocks[:, 0, 0], m[:, 0])[:5000]
+    ref = np.convolve(blocks[:, 0, 0], m[:, 0])[:Nt]
     assert oracle.rel_l2(d.cpu().numpy()[:, 0], ref) <= 1e-12
-    with pytest.raises(bt.BtoepError):
-        bt.btoep_create(np.zeros(((1 << 20) + 1, 1, 1)), "f64")
+    # (F^T d)_j = sum_{i >= j} F_{i-j} d_i: the correlation of d with the block sequence
+    ref_t = np.correlate(m[:, 0], blocks[:, 0, 0], mode="full")[Nt - 1:]
+    assert oracle.rel_l2(mt.cpu().numpy()[:, 0], ref_t) <= 1e-12
+    if Nt == 64827:
+        with pytest.raises(bt.BtoepError) as e:
+            bt.btoep_create(np.zeros((Nt + 1, 1, 1)), "f64")
+        assert e.value.status == 4
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
