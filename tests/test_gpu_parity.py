@@ -247,3 +247,29 @@ def test_every_kernel_variant_and_autotune(bt, storage):
     assert 0 <= t["var_n"] < 6 and 0 <= t["var_c"] < 6 and len(t["ms_n"]) == 6
     with pytest.raises(bt.BtoepError):
         bt.btoep_set_tuning(op, 6, 0)
+
+
+@pytest.mark.parametrize("shape", [(5, 65535, 9), (3, 2, 1000003)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("k", [1, 3])
+def test_extreme_sensor_and_parameter_counts(bt, shape, storage, k):
+    """The largest sensor count the library accepts (65535: a grid dimension of the data-side
+    kernel) and a million ragged parameter columns, single- and multi-vector."""
+    Nt, Nd, Nm = shape
+    print("extreme", shape, storage, k, flush=True)
+    rng = np.random.default_rng(Nd + Nm + k)
+    blocks = rng.standard_normal((Nt, Nd, Nm))
+    op = make(bt, blocks, storage)
+    vn = np.float64 if storage == "f64" else np.float32
+    M = rng.standard_normal((k, Nt, Nm)).astype(vn)
+    D = rng.standard_normal((k, Nt, Nd)).astype(vn)
+    FM = bt.btoep_apply_F(op, to_dev(M, op.vector_dtype)).double().cpu().numpy()
+    FTD = bt.btoep_apply_FT(op, to_dev(D, op.vector_dtype)).double().cpu().numpy()
+    FM_ref = oracle.apply_F(blocks, M.astype(np.float64))
+    FTD_ref = oracle.apply_FT(blocks, D.astype(np.float64))
+    for r in range(k):
+        assert oracle.rel_l2(FM[r], FM_ref[r]) <= TOL[storage]
+        assert oracle.rel_l2(FTD[r], FTD_ref[r]) <= TOL[storage]
+    with pytest.raises(bt.BtoepError) as e:
+        bt.btoep_create(np.zeros((2, 65536, 1)), storage)
+    assert e.value.status == 4
