@@ -315,7 +315,9 @@ btoep_status btoep_profile_read(btoep_op op, btoep_kernel_time* out, int max, in
  * Stepwise CG, for servers that batch the H applications of many solves with other work
  * (paper section 2.2).  The caller applies H itself (btoep_apply_H / btoep_apply_batched on
  * the vectors returned by btoep_cg_vectors) and then calls btoep_cg_update; everything else
- * (inner products in FP64, scalar recurrences, vector updates) runs on the device.
+ * (inner products in FP64, scalar recurrences, vector updates) runs on the device.  Because
+ * the caller forms Ap, a general SPD prior R (section 2.2's prior precision operator) can be
+ * used: apply H with prior_prec = 0 and add R p before the update.
  *   btoep_cg_start : state for k right-hand sides; x (op vector type, [k][Nt][Nm], caller
  *                    owned) is set to 0, r = p = b; stops a right-hand side once
  *                    ||r|| <= rtol ||b|| (recurrence residual).  Allocates its vectors.

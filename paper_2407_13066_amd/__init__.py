@@ -461,6 +461,21 @@ class CgState:
     def ap(self, r):
         return self.ap_ptr + r * self.vec_bytes
 
+    def tensors(self):
+        """Torch views [k][Nt][Nm] of the state's p and Ap arrays (device memory the state owns;
+        valid until end()), for callers that add terms of their own to H p -- e.g. a general
+        prior operator applied by the caller, with H run at prior_prec = 0."""
+        torch = _torch()
+        typestr = "<f8" if self.op.storage == "f64" else "<f4"
+        shape = (self.k, self.op.Nt, self.op.Nm)
+
+        class _View:
+            def __init__(self, ptr):
+                self.__cuda_array_interface__ = {"shape": shape, "typestr": typestr, "data": (ptr, False),
+                                                 "version": 3, "strides": None}
+        return (torch.as_tensor(_View(self.p_ptr), device="cuda"),
+                torch.as_tensor(_View(self.ap_ptr), device="cuda"))
+
     def end(self):
         if self.handle:
             load_library().btoep_cg_end(self.handle)

@@ -123,3 +123,37 @@ def test_cg_workload_nt256_nd64_nm16384(bt):
     for xx in (x[0], x64[0]):
         Hx = oracle.apply_H(blocks, xx, noise_prec, alpha)
         assert np.linalg.norm(b - Hx) / np.linalg.norm(b) <= 1.01e-8
+
+
+def test_stepwise_cg_with_a_caller_applied_prior(bt):
+    """H with a general SPD prior R (here delta I + gamma times a path Laplacian over the
+    parameters, at every time step): the caller runs the library's H at prior_prec = 0 and adds
+    R p itself between the stepwise CG calls; the solution matches a dense solve of
+    (noise_prec A^T A + R) x = b with A the assembled operator."""
+    rng = np.random.default_rng(24)
+    Nt, Nd, Nm = 6, 3, 8
+    blocks = rng.standard_normal((Nt, Nd, Nm))
+    noise_prec, delta, gamma = 2.0, 0.3, 0.7
+    Rp = delta * np.eye(Nm) + gamma * (2 * np.eye(Nm) - np.eye(Nm, k=1) - np.eye(Nm, k=-1))
+    A = pins.dense_matrix(blocks)
+    Hd = noise_prec * A.T @ A + np.kron(np.eye(Nt), Rp)
+    b = rng.standard_normal((1, Nt, Nm))
+    x_ref = np.linalg.solve(Hd, b.ravel()).reshape(Nt, Nm)
+    op = make(bt, blocks, "f64")
+    bd = to_dev(b, torch.float64)
+    x = torch.zeros_like(bd)
+    cg = bt.btoep_cg_start(op, bd, x, 1e-12, noise_prec, 0.0)
+    P, AP = cg.tensors()
+    Rt = torch.from_numpy(Rp).cuda()
+    for _ in range(500):
+        bt.btoep_apply_batched_ptrs(op, "H", [cg.p(0)], [cg.ap(0)], noise_prec, 0.0)
+        AP += torch.matmul(P, Rt)  # R symmetric: (R p_t) for every time step t
+        bt.btoep_cg_update(cg)
+        bt.btoep_cg_poll(cg)
+        torch.cuda.synchronize()
+        ready, active, iters, rel = bt.btoep_cg_status(cg)
+        if ready and active == 0:
+            break
+    assert ready and active == 0, (iters, rel)
+    assert oracle.rel_l2(x[0].cpu().numpy(), x_ref) <= 1e-9
+    bt.btoep_cg_end(cg)
