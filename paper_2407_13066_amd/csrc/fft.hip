@@ -340,10 +340,10 @@ struct CtPlan {
     static constexpr int N = (Rs * ... * 1);
 };
 
-template <typename T, int R, int DIR, int CMAX, int N, int Ns>
-__device__ __forceinline__ void ct_pass(int logP, size_t tw_off) {
+template <typename T, int R, int DIR, int CMAX, int N, int Ns, bool TWL>
+__device__ __forceinline__ void ct_pass(int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
-    const cx<T>* tw = reinterpret_cast<const cx<T>*>(fft_smem + tw_off);
+    const cx<T>* tw = TWL ? reinterpret_cast<const cx<T>*>(fft_smem + tw_off) : twg;
     constexpr int MAXB = (CMAX + R - 1) / R;
     constexpr int NR = N / R;
     constexpr int stride = NR / Ns;
@@ -383,25 +383,15 @@ __device__ __forceinline__ void ct_pass(int logP, size_t tw_off) {
     __syncthreads();
 }
 
-template <typename T, int DIR, int CMAX, int N, int Ns, int R, int... Rest>
-__device__ __forceinline__ void ct_passes(int logP, size_t tw_off) {
-    ct_pass<T, R, DIR, CMAX, N, Ns>(logP, tw_off);
-    if constexpr (sizeof...(Rest) > 0) ct_passes<T, DIR, CMAX, N, Ns * R, Rest...>(logP, tw_off);
+template <typename T, int DIR, int CMAX, bool TWL, int N, int Ns, int R, int... Rest>
+__device__ __forceinline__ void ct_passes(int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
+    ct_pass<T, R, DIR, CMAX, N, Ns, TWL>(logP, tw_off, twg);
+    if constexpr (sizeof...(Rest) > 0) ct_passes<T, DIR, CMAX, TWL, N, Ns * R, Rest...>(logP, tw_off, twg);
 }
 
-template <typename T, int DIR, int CMAX, int... Rs>
-__device__ __forceinline__ void ct_run(CtPlan<Rs...>, int logP, size_t tw_off) {
-    ct_passes<T, DIR, CMAX, CtPlan<Rs...>::N, 1, Rs...>(logP, tw_off);
-}
-
-// Static plans require the twiddles in LDS (the launchers only pick them then).
-template <typename T, int DIR, int CMAX, typename PL>
-__device__ __forceinline__ void run_fft(const FftPlan& plan, int logP, bool twl, size_t tw_off,
-                                        const cx<T>* __restrict__ twg) {
-    if constexpr (PL::kStatic)
-        ct_run<T, DIR, CMAX>(PL{}, logP, tw_off);
-    else
-        fft_lds<T, DIR, CMAX>(plan, logP, twl, tw_off, twg);
+template <typename T, int DIR, int CMAX, bool TWL, int... Rs>
+__device__ __forceinline__ void ct_run(CtPlan<Rs...>, int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
+    ct_passes<T, DIR, CMAX, TWL, CtPlan<Rs...>::N, 1, Rs...>(logP, tw_off, twg);
 }
 
 template <typename T>
@@ -499,17 +489,43 @@ __device__ __forceinline__ const cx<T>* stage_twiddles(size_t data_bytes, bool t
 // LDS a workgroup may use for one column tile plus the twiddle table.
 static constexpr size_t kFftLdsBudget = 64 * 1024;
 
-// Widest tile (log2 columns) the launchers pick for a compile-time plan of length N (twiddles
-// in LDS), and the global loads per thread that then cover one whole tile of N+1 rows.
-template <typename T>
-constexpr int ct_log_cols(int N) {
+// Widest column tile (log2) of a length-N transform with elements of `elem` bytes, with or
+// without the twiddle table in LDS (-1 when not even one column fits).
+constexpr int tile_log_cols(int N, size_t elem, int cmax, bool twl) {
     for (int lp = 6; lp >= 0; --lp) {
         const size_t P = (size_t)1 << lp;
-        if ((size_t)(N + 1) * P * sizeof(cx<T>) + (size_t)2 * N * sizeof(cx<T>) <= kFftLdsBudget &&
-            (size_t)N * P <= (size_t)FftCfg<T>::CMAX * kFftThreads)
+        if ((size_t)(N + 1) * P * elem + (twl ? (size_t)2 * N * elem : 0) <= kFftLdsBudget &&
+            (size_t)N * P <= (size_t)cmax * kFftThreads)
             return lp;
     }
-    return 0;
+    return -1;
+}
+// Twiddles live in LDS when they fit without narrowing the column tile: every global access
+// of a tile is a run of P consecutive columns, and runs shorter than a cache line cost more
+// than twiddle reads from the caches.
+constexpr bool tile_twl(int N, size_t elem, int cmax) {
+    const int with = tile_log_cols(N, elem, cmax, true);
+    return with >= 0 && with >= tile_log_cols(N, elem, cmax, false);
+}
+// The same rules for a compile-time plan of length N: where its twiddles live, the widest tile
+// the launchers pick, and the global loads per thread that then cover one tile of N+1 rows.
+template <typename T>
+constexpr bool ct_twl(int N) {
+    return tile_twl(N, sizeof(cx<T>), FftCfg<T>::CMAX);
+}
+template <typename T>
+constexpr int ct_log_cols(int N) {
+    const int lp = tile_log_cols(N, sizeof(cx<T>), FftCfg<T>::CMAX, ct_twl<T>(N));
+    return lp < 0 ? 0 : lp;
+}
+
+template <typename T, int DIR, int CMAX, typename PL>
+__device__ __forceinline__ void run_fft(const FftPlan& plan, int logP, bool twl, size_t tw_off,
+                                        const cx<T>* __restrict__ twg) {
+    if constexpr (PL::kStatic)
+        ct_run<T, DIR, CMAX, ct_twl<T>(PL::N)>(PL{}, logP, tw_off, twg);
+    else
+        fft_lds<T, DIR, CMAX>(plan, logP, twl, tw_off, twg);
 }
 template <typename T, typename PL, bool STATIC = PL::kStatic>
 struct LoadSlots {
@@ -598,7 +614,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 }
 
 // Setup form (operator block column, FP64 in, batch over rows s with explicit strides).
-template <typename So>
+template <typename So, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fft_r2c_strided(const double* __restrict__ in, int64_t in_row,
                                                                  int64_t in_batch, So* __restrict__ out,
                                                                  int64_t out_row, int64_t out_batch, int Nt,
@@ -610,12 +626,12 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<double>);
     const double* __restrict__ x = in + (int64_t)blockIdx.y * in_batch;
     So* __restrict__ y = out + (int64_t)blockIdx.y * out_batch;
-    RealTile<double, double, FftCfg<double>::CMAX> tile;
+    RealTile<double, double, LoadSlots<double, PL>::value> tile;
     tile.load(x, in_row, Nt << logP, logP, col0, ncols);
     const cx<double>* tw = stage_twiddles<double>(tw_off, twl, N, twg);
     tile.commit(reinterpret_cast<double*>(fft_smem), Nt, N, logP, col0, ncols);
     __syncthreads();
-    fft_lds<double, -1, FftCfg<double>::CMAX>(plan, logP, twl, tw_off, twg);
+    run_fft<double, -1, FftCfg<double>::CMAX, PL>(plan, logP, twl, tw_off, twg);
     for (int e = threadIdx.x; e < (N + 1) << logP; e += kFftThreads) {
         const int c = e & (P - 1), f = e >> logP;
         if (col0 + c < ncols) put(&y[(int64_t)f * out_row + col0 + c], r2c_bin(sh, N, logP, f, c, tw));
@@ -730,27 +746,9 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 static size_t elem_of(Real r) { return r == Real::F64 ? 16 : 8; }
 static int cmax_of(Real r) { return r == Real::F64 ? FftCfg<double>::CMAX : FftCfg<float>::CMAX; }
 
-// Widest column tile (log2) of a length-N transform, with or without the twiddle table in LDS.
-static int max_log_cols(int N, Real r, bool twl) {
-    const size_t elem = elem_of(r);
-    const size_t tw = twl ? (size_t)2 * N * elem : 0;
-    for (int lp = 6; lp >= 0; --lp) {
-        const size_t P = (size_t)1 << lp;
-        if ((size_t)(N + 1) * P * elem + tw <= kFftLdsBudget && (size_t)N * P <= (size_t)cmax_of(r) * kFftThreads)
-            return lp;
-    }
-    return -1;
-}
+static bool twl_of(int N, Real r) { return tile_twl(N, elem_of(r), cmax_of(r)); }
 
-// Twiddles live in LDS when they fit without narrowing the column tile: every global access
-// of a tile is a run of P consecutive columns, and runs shorter than a cache line cost more
-// than twiddle reads from the caches.
-static bool twl_of(int N, Real r) {
-    const int with = max_log_cols(N, r, true);
-    return with >= 0 && with >= max_log_cols(N, r, false);
-}
-
-int fft_log_cols(int N, Real r) { return max_log_cols(N, r, twl_of(N, r)); }
+int fft_log_cols(int N, Real r) { return tile_log_cols(N, elem_of(r), cmax_of(r), twl_of(N, r)); }
 
 size_t fft_lds_bytes(int N, int logP, Real r) {
     const size_t elem = elem_of(r);
@@ -800,17 +798,36 @@ typedef CtPlan<4, 5, 3, 7> Plan420f;
     X(4, Plan420f)              \
     X(5, Plan512)
 
-// Index of the compile-time plan of `plan`'s length (FP32 kernels with LDS twiddles), or -1;
-// the same index selects the plan of that length in either table.
+// FP64 transforms (double registers: plans of radix at most 16), for the benchmarked lengths
+// N = 420, 1000, 2000 and 4000.
+typedef CtPlan<8, 5, 5, 5> Plan1000d;
+typedef CtPlan<16, 5, 5, 5> Plan2000d;
+typedef CtPlan<16, 5, 5, 5, 2> Plan4000d;
+#define BT_STATIC_PLANS64(X) \
+    X(0, Plan420f)           \
+    X(1, Plan1000d)          \
+    X(2, Plan2000d)          \
+    X(3, Plan4000d)
+
+// Index of the compile-time plan of `plan`'s length in the table of its precision, or -1; for
+// FP32 the same index selects the plan of that length in the vector-side or the fine table.
 static int static_plan_id(const FftPlan& p, Real r) {
-    if (r != Real::F32 || !twl_of(p.N, r)) return -1;
     // the kernels size their load slots for the widest tile fft_log_cols allows
     static_assert(ct_log_cols<float>(420) == 4 && LoadSlots<float, Plan420>::value == 14, "tile rule");
+    static_assert(ct_log_cols<double>(420) == 3 && !ct_twl<double>(420) && LoadSlots<double, Plan420f>::value == 7,
+                  "tile rule");
+    static_assert(ct_log_cols<double>(2000) == 1 && LoadSlots<double, Plan2000d>::value == 8 &&
+                      ct_log_cols<double>(4000) == 0 && LoadSlots<double, Plan4000d>::value == 8,
+                  "tile rule");
     // a compile-time plan applies to any transform of its length (its own radices replace
     // the runtime factorisation; the twiddle table depends on N only)
 #define BT_MATCH(ID, PLAN) \
     if (p.N == PLAN::N) return ID;
-    BT_STATIC_PLANS(BT_MATCH)
+    if (r == Real::F32) {
+        BT_STATIC_PLANS(BT_MATCH)
+    } else {
+        BT_STATIC_PLANS64(BT_MATCH)
+    }
 #undef BT_MATCH
     return -1;
 }
@@ -838,8 +855,17 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
         }
 #undef BT_R2C
     } else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128) {
-        k_fft_r2c<double, double, cx<double>, RuntimePlan><<<grid, block, lds, st>>>(
-            in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, plan, lp, (const cx<double>*)tw, twl, 0);
+#define BT_R2C64(PLAN)                                                                                   \
+    k_fft_r2c<double, double, cx<double>, PLAN><<<grid, block, lds, st>>>(                               \
+        in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, plan, lp, (const cx<double>*)tw, twl, 0)
+        switch (static_plan_id(plan, r)) {
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_R2C64(PLAN); break;
+            BT_STATIC_PLANS64(BT_CASE)
+#undef BT_CASE
+            default: BT_R2C64(RuntimePlan); break;
+        }
+#undef BT_R2C64
     } else {
         return hipErrorInvalidValue;
     }
@@ -856,20 +882,37 @@ hipError_t launch_fft_r2c_strided(Stor os, const double* in, int64_t in_row, int
     dim3 grid(nblk(ncols, lp), nb), block(kFftThreads);
     const size_t lds = fft_lds_bytes(plan.N, lp, Real::F64);
     const cx<double>* tw = (const cx<double>*)tw64;
+    const int pid = static_plan_id(plan, Real::F64);
+#define BT_STR(SO, PLAN)                                                                                \
+    k_fft_r2c_strided<SO, PLAN><<<grid, block, lds, st>>>(in, in_row, in_batch, (SO*)out, out_row, out_batch, \
+                                                          Nt, ncols, plan, lp, tw, twl)
+#define BT_STR_PLAN(SO)                    \
+    switch (pid) {                         \
+        BT_STATIC_PLANS64(BT_CASE)         \
+        default: BT_STR(SO, RuntimePlan); break; \
+    }
     switch (os) {
         case Stor::C128:
-            k_fft_r2c_strided<cx<double>><<<grid, block, lds, st>>>(in, in_row, in_batch, (cx<double>*)out,
-                                                                     out_row, out_batch, Nt, ncols, plan, lp, tw, twl);
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_STR(cx<double>, PLAN); break;
+            BT_STR_PLAN(cx<double>)
+#undef BT_CASE
             break;
         case Stor::C64:
-            k_fft_r2c_strided<cx<float>><<<grid, block, lds, st>>>(in, in_row, in_batch, (cx<float>*)out, out_row,
-                                                                    out_batch, Nt, ncols, plan, lp, tw, twl);
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_STR(cx<float>, PLAN); break;
+            BT_STR_PLAN(cx<float>)
+#undef BT_CASE
             break;
         case Stor::BF16:
-            k_fft_r2c_strided<bf16c><<<grid, block, lds, st>>>(in, in_row, in_batch, (bf16c*)out, out_row,
-                                                                out_batch, Nt, ncols, plan, lp, tw, twl);
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_STR(bf16c, PLAN); break;
+            BT_STR_PLAN(bf16c)
+#undef BT_CASE
             break;
     }
+#undef BT_STR_PLAN
+#undef BT_STR
     return hipGetLastError();
 }
 
@@ -896,10 +939,18 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
         }
 #undef BT_C2R
     } else {
-        k_fft_c2r<double, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out,
-                                                                 out_row, add, add_scale, Nt, ncols, plan, lp,
-                                                                 (const cx<double>*)tw, twl, out_scale,
-                                                                 (8 << lp) >= 64);
+#define BT_C2R64(PLAN)                                                                                          \
+    k_fft_c2r<double, PLAN><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out, out_row, add, \
+                                                      add_scale, Nt, ncols, plan, lp, (const cx<double>*)tw, twl, \
+                                                      out_scale, (8 << lp) >= 64)
+        switch (static_plan_id(plan, r)) {
+#define BT_CASE(ID, PLAN) \
+    case ID: BT_C2R64(PLAN); break;
+            BT_STATIC_PLANS64(BT_CASE)
+#undef BT_CASE
+            default: BT_C2R64(RuntimePlan); break;
+        }
+#undef BT_C2R64
     }
     return hipGetLastError();
 }
@@ -985,21 +1036,38 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int col0 = blockIdx.x << logP, n2 = blockIdx.y, b = blockIdx.z;
     const Tin* __restrict__ x = batch_base<Tin>(in, in_batch, b);
     const int total = N1 << logP;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    // every load of the tile in flight at once (the launcher keeps N1 P <= CMAX threads)
+    constexpr int K = FftCfg<T>::CMAX;
+    T vre[K], vim[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int e = min(threadIdx.x + u * kFftThreads, total - 1);
         const int c = e & P1, n1 = e >> logP;
         const int64_t j = 2 * ((int64_t)N2 * n1 + n2);
         const int col = min(col0 + c, ncols - 1);
-        const bool ok = col0 + c < ncols;
-        const T re = (ok && j < Nt) ? (T)x[j * in_row + col] : (T)0;
-        const T im = (ok && j + 1 < Nt) ? (T)x[(j + 1) * in_row + col] : (T)0;
-        sh[e] = cx<T>{re, im};
+        vre[u] = (T)x[min(j, (int64_t)Nt - 1) * in_row + col];
+        vim[u] = (T)x[min(j + 1, (int64_t)Nt - 1) * in_row + col];
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        if (e < total) {
+            const int c = e & P1, n1 = e >> logP;
+            const int64_t j = 2 * ((int64_t)N2 * n1 + n2);
+            const bool ok = col0 + c < ncols;
+            sh[e] = cx<T>{(ok && j < Nt) ? vre[u] : (T)0, (ok && j + 1 < Nt) ? vim[u] : (T)0};
+        }
     }
     __syncthreads();
     fft_lds<T, -1, FftCfg<T>::CMAX>(p1, logP, false, 0, tw1);
     cx<T>* __restrict__ yb = y + (int64_t)b * y_batch;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
-        const int c = e & P1, k1 = e >> logP;
-        if (col0 + c < ncols) yb[((int64_t)k1 * N2 + n2) * y_row + col0 + c] = cmul(sh[e], twN[2 * n2 * k1]);
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        if (e < total) {
+            const int c = e & P1, k1 = e >> logP;
+            if (col0 + c < ncols) yb[((int64_t)k1 * N2 + n2) * y_row + col0 + c] = cmul(sh[e], twN[2 * n2 * k1]);
+        }
     }
 }
 
@@ -1021,16 +1089,29 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const bool paired = a != 0 && 2 * a != N1;
     const cx<T>* __restrict__ yb = y + (int64_t)b * y_batch;
     const int total = N2 << lq;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
-        const int cc = e & (2 * P - 1), n2 = e >> lq;
-        const int c = cc & P1, k1 = pair_k1(a, cc >> logP, N1);
-        const int col = min(col0 + c, ncols - 1);
-        sh[e] = yb[((int64_t)k1 * N2 + n2) * y_row + col];
+    constexpr int K = FftCfg<T>::CMAX;  // the launcher keeps N2 x 2P <= CMAX threads
+    {
+        cx<T> v[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = min(threadIdx.x + u * kFftThreads, total - 1);
+            const int cc = e & (2 * P - 1), n2 = e >> lq;
+            const int c = cc & P1, k1 = pair_k1(a, cc >> logP, N1);
+            v[u] = yb[((int64_t)k1 * N2 + n2) * y_row + min(col0 + c, ncols - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = threadIdx.x + u * kFftThreads;
+            if (e < total) sh[e] = v[u];
+        }
     }
     __syncthreads();
     fft_lds<T, -1, FftCfg<T>::CMAX>(p2, lq, false, 0, tw2);
     So* __restrict__ ob = out + (int64_t)b * out_batch;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        if (e >= total) continue;
         const int cc = e & (2 * P - 1), k2 = e >> lq;
         const int blk = cc >> logP, c = cc & P1;
         if (col0 + c >= ncols) continue;
@@ -1072,18 +1153,27 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const bool paired = a != 0 && 2 * a != N1;
     const cx<T>* __restrict__ bb = bins + (int64_t)b * b_batch;
     const int total = N2 << lq;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
-        const int cc = e & (2 * P - 1), k2 = e >> lq;
-        const int blk = cc >> logP, c = cc & P1, k1 = pair_k1(a, blk, N1);
-        const int col = min(col0 + c, ncols - 1);
-        int f = k1 + N1 * k2;
-        if (a == 0 && blk == 1 && k2 == 0) f = N;  // Y_N, the partner of Y_0
-        sh[e] = bb[(int64_t)f * b_row + col];
+    // the launcher keeps N2 x 2P <= CMAX threads, so K slots per thread hold the whole tile
+    constexpr int K = FftCfg<T>::CMAX;
+    {
+        cx<T> v[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = min(threadIdx.x + u * kFftThreads, total - 1);
+            const int cc = e & (2 * P - 1), k2 = e >> lq;
+            const int blk = cc >> logP, c = cc & P1, k1 = pair_k1(a, blk, N1);
+            int f = k1 + N1 * k2;
+            if (a == 0 && blk == 1 && k2 == 0) f = N;  // Y_N, the partner of Y_0
+            v[u] = bb[(int64_t)f * b_row + min(col0 + c, ncols - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = threadIdx.x + u * kFftThreads;
+            if (e < total) sh[e] = v[u];
+        }
     }
     __syncthreads();
-    // split: every element reads itself and its partner, then all write (the launcher keeps
-    // N2 x 2P <= CMAX threads, so K slots per thread hold them all)
-    constexpr int K = FftCfg<T>::CMAX;
+    // split: every element reads itself and its partner, then all write
     cx<T> zf[K];
 #pragma unroll
     for (int u2 = 0; u2 < K; ++u2) {
@@ -1117,7 +1207,10 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     __syncthreads();
     fft_lds<T, 1, FftCfg<T>::CMAX>(p2, lq, false, 0, tw2);
     cx<T>* __restrict__ ub = u + (int64_t)b * u_batch;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+#pragma unroll
+    for (int u2 = 0; u2 < K; ++u2) {
+        const int e = threadIdx.x + u2 * kFftThreads;
+        if (e >= total) continue;
         const int cc = e & (2 * P - 1), n2 = e >> lq;
         const int blk = cc >> logP, c = cc & P1;
         if (col0 + c >= ncols || (blk == 1 && !paired)) continue;
@@ -1137,15 +1230,29 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int col0 = blockIdx.x << logP, n2 = blockIdx.y, b = blockIdx.z;
     const cx<T>* __restrict__ ub = u + (int64_t)b * u_batch;
     const int total = N1 << logP;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
-        const int c = e & P1, k1 = e >> logP;
-        sh[e] = ub[((int64_t)k1 * N2 + n2) * u_row + min(col0 + c, ncols - 1)];
+    constexpr int K = FftCfg<T>::CMAX;  // the launcher keeps N1 P <= CMAX threads
+    {
+        cx<T> v[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = min(threadIdx.x + u * kFftThreads, total - 1);
+            const int c = e & P1, k1 = e >> logP;
+            v[u] = ub[((int64_t)k1 * N2 + n2) * u_row + min(col0 + c, ncols - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = threadIdx.x + u * kFftThreads;
+            if (e < total) sh[e] = v[u];
+        }
     }
     __syncthreads();
     fft_lds<T, 1, FftCfg<T>::CMAX>(p1, logP, false, 0, tw1);
     T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.at(b)));
     const T* __restrict__ ad = static_cast<const T*>(add.at(b));
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        if (e >= total) continue;
         const int c = e & P1, n1 = e >> logP;
         if (col0 + c >= ncols) continue;
         const int64_t j = 2 * ((int64_t)N2 * n1 + n2);

@@ -54,7 +54,9 @@ def test_every_pin_through_the_gpu_path(bt):
 # FFT column tiles and several spans, and every transform length with a compile-time plan
 # (N = 32, 64, 128, 256, 420, 512) next to runtime-plan lengths
 RAGGED = [(1, 1, 1), (2, 3, 5), (11, 5, 13), (13, 7, 1000), (37, 9, 300), (64, 100, 4099), (45, 3, 9001),
-          (128, 50, 2000), (17, 130, 257), (512, 3, 700), (256, 12, 333), (420, 5, 1111)]
+          (128, 50, 2000), (17, 130, 257), (512, 3, 700), (256, 12, 333), (420, 5, 1111),
+          # lengths with compile-time FP64 plans (setup of every storage, FP64 vector transforms)
+          (1000, 2, 129), (2000, 3, 77), (4000, 2, 37)]
 
 
 @pytest.mark.parametrize("shape", RAGGED)
