@@ -780,13 +780,21 @@ typedef CtPlan<8, 16> Plan128;
 typedef CtPlan<16, 16> Plan256;
 typedef CtPlan<20, 21> Plan420;
 typedef CtPlan<8, 8, 8> Plan512;
+typedef CtPlan<8, 5, 5, 5> Plan1000d;
+typedef CtPlan<16, 5, 5, 5> Plan2000d;
+typedef CtPlan<16, 5, 5, 5, 2> Plan4000d;
+typedef CtPlan<20, 20, 5> Plan2000;
+typedef CtPlan<20, 20, 5, 2> Plan4000;
 #define BT_STATIC_PLANS(X) \
     X(0, Plan32)           \
     X(1, Plan64)           \
     X(2, Plan128)          \
     X(3, Plan256)          \
     X(4, Plan420)          \
-    X(5, Plan512)
+    X(5, Plan512)          \
+    X(6, Plan1000d)        \
+    X(7, Plan2000)         \
+    X(8, Plan4000)
 typedef CtPlan<8, 8, 2> Plan128f;
 typedef CtPlan<8, 8, 4> Plan256f;
 typedef CtPlan<4, 5, 3, 7> Plan420f;
@@ -796,13 +804,22 @@ typedef CtPlan<4, 5, 3, 7> Plan420f;
     X(2, Plan128f)              \
     X(3, Plan256f)              \
     X(4, Plan420f)              \
-    X(5, Plan512)
+    X(5, Plan512)               \
+    X(6, Plan1000d)             \
+    X(7, Plan2000d)             \
+    X(8, Plan4000d)
+
+// FP64 data-side kernel (two transforms in one kernel): radices of at most 8.
+typedef CtPlan<8, 5, 5, 5, 2> Plan2000df;
+typedef CtPlan<8, 5, 5, 5, 4> Plan4000df;
+#define BT_STATIC_PLANS64_FINE(X) \
+    X(0, Plan420f)                \
+    X(1, Plan1000d)               \
+    X(2, Plan2000df)              \
+    X(3, Plan4000df)
 
 // FP64 transforms (double registers: plans of radix at most 16), for the benchmarked lengths
 // N = 420, 1000, 2000 and 4000.
-typedef CtPlan<8, 5, 5, 5> Plan1000d;
-typedef CtPlan<16, 5, 5, 5> Plan2000d;
-typedef CtPlan<16, 5, 5, 5, 2> Plan4000d;
 #define BT_STATIC_PLANS64(X) \
     X(0, Plan420f)           \
     X(1, Plan1000d)          \
@@ -818,6 +835,10 @@ static int static_plan_id(const FftPlan& p, Real r) {
                   "tile rule");
     static_assert(ct_log_cols<double>(2000) == 1 && LoadSlots<double, Plan2000d>::value == 8 &&
                       ct_log_cols<double>(4000) == 0 && LoadSlots<double, Plan4000d>::value == 8,
+                  "tile rule");
+    static_assert(ct_log_cols<float>(1000) == 3 && LoadSlots<float, Plan1000d>::value == 16 &&
+                      ct_log_cols<float>(2000) == 2 && LoadSlots<float, Plan2000>::value == 16 &&
+                      ct_log_cols<float>(4000) == 1 && LoadSlots<float, Plan4000>::value == 16,
                   "tile rule");
     // a compile-time plan applies to any transform of its length (its own radices replace
     // the runtime factorisation; the twiddle table depends on N only)
@@ -988,16 +1009,28 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
         }
 #undef BT_DS
     } else {
-        if (dout)
-            k_dside<double, false, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)part, nspan,
-                                                                          part_batch, d, (cx<double>*)dh,
-                                                                          dh_batch, Nt, Nd, plan,
-                                                                          (const cx<double>*)tw, twl, scale);
-        else
-            k_dside<double, true, RuntimePlan><<<grid, block, lds, st>>>((const cx<double>*)part, nspan,
-                                                                         part_batch, d, (cx<double>*)dh,
-                                                                         dh_batch, Nt, Nd, plan,
-                                                                         (const cx<double>*)tw, twl, scale);
+#define BT_DS64(MODE, PLAN)                                                                                   \
+    k_dside<double, MODE, PLAN><<<grid, block, lds, st>>>((const cx<double>*)part, nspan, part_batch, d,      \
+                                                          (cx<double>*)dh, dh_batch, Nt, Nd, plan,            \
+                                                          (const cx<double>*)tw, twl, scale)
+        switch (static_plan_id(plan, r)) {
+#define BT_CASE(ID, PLAN)         \
+    case ID:                      \
+        if (dout)                 \
+            BT_DS64(false, PLAN); \
+        else                      \
+            BT_DS64(true, PLAN);  \
+        break;
+            BT_STATIC_PLANS64_FINE(BT_CASE)
+#undef BT_CASE
+            default:
+                if (dout)
+                    BT_DS64(false, RuntimePlan);
+                else
+                    BT_DS64(true, RuntimePlan);
+                break;
+        }
+#undef BT_DS64
     }
     return hipGetLastError();
 }
