@@ -75,7 +75,7 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
-def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, check_cols=1):
+def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, check_cols=1, storages=("f32", "bf16", "f64")):
     """H applies with k stacked right-hand sides on the FP32-, BF16- and FP64-stored operator
     (matrix-core products); per-right-hand-side time against the single-vector H of the same
     storage, matrix-core throughput of the products, and the error of sampled columns against
@@ -85,7 +85,7 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, check_cols=1):
     import synth
     Nt, Nd, Nm = blocks.shape
     out = {}
-    for storage in ("f32", "bf16", "f64"):
+    for storage in storages:
         op = op32 if storage == "f32" else bt.btoep_create(blocks, storage)
         vn = np.float64 if storage == "f64" else np.float32
         res = {}
@@ -481,6 +481,8 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solve measurement")
     ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape (FP64) context runs")
     ap.add_argument("--no-setup", action="store_true", help="skip the setup (block transform) measurement")
+    ap.add_argument("--multi-rhs-storage", default="f32,bf16,f64",
+                    help="operator storages of the multi-RHS measurement (comma separated)")
     ap.add_argument("--no-appendix", action="store_true",
                     help="skip the comparison with the paper's appendix (SOTI) matvec form")
     ap.add_argument("--cpu-sample-cols", type=int, default=65536,
@@ -662,7 +664,8 @@ def main():
 
     if args.multi_rhs:
         ks = [int(v) for v in args.multi_rhs.split(",") if v]
-        result["multi_rhs"] = multi_rhs_benchmark(bt, blocks, op, ks, ms_per_step)
+        result["multi_rhs"] = multi_rhs_benchmark(bt, blocks, op, ks, ms_per_step,
+                                                  storages=[v for v in args.multi_rhs_storage.split(",") if v])
 
     op.destroy()
     torch.cuda.empty_cache()
