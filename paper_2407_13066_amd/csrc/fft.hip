@@ -1052,6 +1052,16 @@ hipError_t launch_dside(Real r, const void* part, int nspan, int64_t part_batch,
 // the runtime plans with their own twiddle tables exp(-2 pi i t / (2 Nsub)); twN is the
 // operator's table exp(-2 pi i t / (2N)).
 
+// Sub-transforms of the four-step passes: a compile-time plan when one exists for the length
+// (twiddles read through the caches: these kernels keep no table in LDS), else the runtime plan.
+template <typename T, int DIR, typename PL>
+__device__ __forceinline__ void sub_fft(const FftPlan& p, int logP, const cx<T>* __restrict__ tw) {
+    if constexpr (PL::kStatic)
+        ct_run<T, DIR, FftCfg<T>::CMAX, false>(PL{}, logP, 0, tw);
+    else
+        fft_lds<T, DIR, FftCfg<T>::CMAX>(p, logP, false, 0, tw);
+}
+
 // Input base of batch b: in.at(b), or in.at(0) + b * in_batch when in_batch != 0.
 template <typename T>
 __device__ __forceinline__ const T* batch_base(const PtrBatch& in, int64_t in_batch, int b) {
@@ -1060,7 +1070,7 @@ __device__ __forceinline__ const T* batch_base(const PtrBatch& in, int64_t in_ba
 
 // A: z[n] = x[2n] + i x[2n+1] (zero for rows >= Nt) at n = N2 n1 + n2 for one n2 (blockIdx.y);
 // forward N1-point transform over n1; times W_N^{n2 k1}; y[b][k1 N2 + n2][c].
-template <typename T, typename Tin>
+template <typename T, typename Tin, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_a(
     PtrBatch in, int64_t in_batch, int64_t in_row, int Nt, int ncols, cx<T>* __restrict__ y, int64_t y_row,
     int64_t y_batch, FftPlan p1, int N2, int logP, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ twN) {
@@ -1092,7 +1102,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
         }
     }
     __syncthreads();
-    fft_lds<T, -1, FftCfg<T>::CMAX>(p1, logP, false, 0, tw1);
+    sub_fft<T, -1, PL>(p1, logP, tw1);
     cx<T>* __restrict__ yb = y + (int64_t)b * y_batch;
 #pragma unroll
     for (int u = 0; u < K; ++u) {
@@ -1111,7 +1121,7 @@ __device__ __forceinline__ int pair_k1(int a, int blk, int N1) { return blk ? (N
 
 // B: forward N2-point transforms of rows k1 N2 + n2 for k1 = a and N1 - a, then the split into
 // bins X_f = (Z_f + conj Z_{N-f}) / 2 + W_{2N}^f (Z_f - conj Z_{N-f}) / (2i), f = k1 + N1 k2.
-template <typename T, typename So>
+template <typename T, typename So, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_b(
     const cx<T>* __restrict__ y, int64_t y_row, int64_t y_batch, So* __restrict__ out, int64_t out_row,
     int64_t out_batch, int ncols, FftPlan p2, int N1, int logP, const cx<T>* __restrict__ tw2,
@@ -1139,7 +1149,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
         }
     }
     __syncthreads();
-    fft_lds<T, -1, FftCfg<T>::CMAX>(p2, lq, false, 0, tw2);
+    sub_fft<T, -1, PL>(p2, lq, tw2);
     So* __restrict__ ob = out + (int64_t)b * out_batch;
 #pragma unroll
     for (int u = 0; u < K; ++u) {
@@ -1175,7 +1185,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 // a == 0) into Z_f = E_f + i O_f, E_f = (Y_f + conj Y_{N-f}) / 2,
 // O_f = (Y_f - conj Y_{N-f}) / 2 W_{2N}^{-f}; inverse N2-point transforms over k2; times
 // W_N^{-n2 k1}; u[b][k1 N2 + n2][c].
-template <typename T>
+template <typename T, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_c(
     const cx<T>* __restrict__ bins, int64_t b_row, int64_t b_batch, cx<T>* __restrict__ u, int64_t u_row,
     int64_t u_batch, int ncols, FftPlan p2, int N1, int logP, const cx<T>* __restrict__ tw2,
@@ -1238,7 +1248,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
         if (e < total) sh[e] = zf[u2];
     }
     __syncthreads();
-    fft_lds<T, 1, FftCfg<T>::CMAX>(p2, lq, false, 0, tw2);
+    sub_fft<T, 1, PL>(p2, lq, tw2);
     cx<T>* __restrict__ ub = u + (int64_t)b * u_batch;
 #pragma unroll
     for (int u2 = 0; u2 < K; ++u2) {
@@ -1254,7 +1264,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
 
 // D: inverse N1-point transforms over k1 of rows k1 N2 + n2 for one n2 (blockIdx.y), giving
 // z[N2 n1 + n2]; out rows 2n and 2n + 1 (< Nt) = out_scale * (Re, Im) (+ add_scale * addend).
-template <typename T>
+template <typename T, typename PL>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_long_d(
     const cx<T>* __restrict__ u, int64_t u_row, int64_t u_batch, PtrBatch out, int64_t out_row, PtrBatch add,
     T add_scale, int Nt, int ncols, FftPlan p1, int N2, int logP, const cx<T>* __restrict__ tw1, T out_scale) {
@@ -1279,7 +1289,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
         }
     }
     __syncthreads();
-    fft_lds<T, 1, FftCfg<T>::CMAX>(p1, logP, false, 0, tw1);
+    sub_fft<T, 1, PL>(p1, logP, tw1);
     T* __restrict__ x = static_cast<T*>(const_cast<void*>(out.at(b)));
     const T* __restrict__ ad = static_cast<const T*>(add.at(b));
 #pragma unroll
@@ -1338,6 +1348,28 @@ static int long_pick_cols(int N1, int N2, Real r, int ncols, int nb) {
     return lp;
 }
 
+// Compile-time plans of the four-step sub-lengths (N = 10000 = 100 x 100 and 5000 = 50 x 100).
+typedef CtPlan<4, 5, 5> Sub100d;
+typedef CtPlan<20, 5> Sub100f;
+typedef CtPlan<2, 5, 5> Sub50;
+// Calls fn(plan tag) with the sub-plan of length N for precision T (RuntimePlan when none).
+template <typename T, typename Fn>
+static void with_sub_plan(int N, Fn&& fn) {
+    if (N == 100) {
+        if constexpr (sizeof(T) == 8)
+            fn(Sub100d{});
+        else
+            fn(Sub100f{});
+    } else if (N == 50) {
+        if constexpr (sizeof(T) == 8)
+            fn(Sub50{});
+        else
+            fn(RuntimePlan{});  // FP32: radix-2 passes with 16 values per thread spill
+    } else {
+        fn(RuntimePlan{});
+    }
+}
+
 hipError_t launch_long_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t in_batch, int64_t in_row, int nb,
                            int Nt, int ncols, void* tmp, int64_t tmp_row, int64_t tmp_batch, void* out,
                            int64_t out_row, int64_t out_batch, const FftPlan& p1, const FftPlan& p2, const void* tw1,
@@ -1350,33 +1382,42 @@ hipError_t launch_long_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t
     const size_t lds_a = ((size_t)N1 << lp) * elem, lds_b = ((size_t)N2 << (lp + 1)) * elem;
     dim3 ga(nt, N2, nb), gb(nt, N1 / 2 + 1, nb), block(kFftThreads);
     if (r == Real::F32 && ir == Real::F32 && os == Stor::C64) {
-        k_long_a<float, float><<<ga, block, lds_a, st>>>(in, in_batch, in_row, Nt, ncols, (cx<float>*)tmp, tmp_row,
-                                                         tmp_batch, p1, N2, lp, (const cx<float>*)tw1,
-                                                         (const cx<float>*)twN);
-        k_long_b<float, cx<float>><<<gb, block, lds_b, st>>>((const cx<float>*)tmp, tmp_row, tmp_batch,
-                                                             (cx<float>*)out, out_row, out_batch, ncols, p2, N1, lp,
-                                                             (const cx<float>*)tw2, (const cx<float>*)twN);
+        with_sub_plan<float>(N1, [&](auto pl) {
+            k_long_a<float, float, decltype(pl)><<<ga, block, lds_a, st>>>(
+                in, in_batch, in_row, Nt, ncols, (cx<float>*)tmp, tmp_row, tmp_batch, p1, N2, lp,
+                (const cx<float>*)tw1, (const cx<float>*)twN);
+        });
+        with_sub_plan<float>(N2, [&](auto pl) {
+            k_long_b<float, cx<float>, decltype(pl)><<<gb, block, lds_b, st>>>(
+                (const cx<float>*)tmp, tmp_row, tmp_batch, (cx<float>*)out, out_row, out_batch, ncols, p2, N1, lp,
+                (const cx<float>*)tw2, (const cx<float>*)twN);
+        });
     } else if (r == Real::F64 && ir == Real::F64) {
-        k_long_a<double, double><<<ga, block, lds_a, st>>>(in, in_batch, in_row, Nt, ncols, (cx<double>*)tmp,
-                                                           tmp_row, tmp_batch, p1, N2, lp, (const cx<double>*)tw1,
-                                                           (const cx<double>*)twN);
+        with_sub_plan<double>(N1, [&](auto pl) {
+            k_long_a<double, double, decltype(pl)><<<ga, block, lds_a, st>>>(
+                in, in_batch, in_row, Nt, ncols, (cx<double>*)tmp, tmp_row, tmp_batch, p1, N2, lp,
+                (const cx<double>*)tw1, (const cx<double>*)twN);
+        });
         const cx<double>* t = (const cx<double>*)tmp;
         const cx<double>* w2 = (const cx<double>*)tw2;
         const cx<double>* wN = (const cx<double>*)twN;
-        switch (os) {
-            case Stor::C128:
-                k_long_b<double, cx<double>><<<gb, block, lds_b, st>>>(t, tmp_row, tmp_batch, (cx<double>*)out,
-                                                                       out_row, out_batch, ncols, p2, N1, lp, w2, wN);
-                break;
-            case Stor::C64:
-                k_long_b<double, cx<float>><<<gb, block, lds_b, st>>>(t, tmp_row, tmp_batch, (cx<float>*)out,
-                                                                      out_row, out_batch, ncols, p2, N1, lp, w2, wN);
-                break;
-            case Stor::BF16:
-                k_long_b<double, bf16c><<<gb, block, lds_b, st>>>(t, tmp_row, tmp_batch, (bf16c*)out, out_row,
-                                                                  out_batch, ncols, p2, N1, lp, w2, wN);
-                break;
-        }
+        with_sub_plan<double>(N2, [&](auto pl) {
+            using PL = decltype(pl);
+            switch (os) {
+                case Stor::C128:
+                    k_long_b<double, cx<double>, PL><<<gb, block, lds_b, st>>>(
+                        t, tmp_row, tmp_batch, (cx<double>*)out, out_row, out_batch, ncols, p2, N1, lp, w2, wN);
+                    break;
+                case Stor::C64:
+                    k_long_b<double, cx<float>, PL><<<gb, block, lds_b, st>>>(
+                        t, tmp_row, tmp_batch, (cx<float>*)out, out_row, out_batch, ncols, p2, N1, lp, w2, wN);
+                    break;
+                case Stor::BF16:
+                    k_long_b<double, bf16c, PL><<<gb, block, lds_b, st>>>(
+                        t, tmp_row, tmp_batch, (bf16c*)out, out_row, out_batch, ncols, p2, N1, lp, w2, wN);
+                    break;
+            }
+        });
     } else {
         return hipErrorInvalidValue;
     }
@@ -1396,19 +1437,27 @@ hipError_t launch_long_c2r(Real r, const void* in, int64_t in_row, int64_t in_ba
     const size_t lds_d = ((size_t)N1 << lp) * elem, lds_c = ((size_t)N2 << (lp + 1)) * elem;
     dim3 gc(nt, N1 / 2 + 1, nb), gd(nt, N2, nb), block(kFftThreads);
     if (r == Real::F32) {
-        k_long_c<float><<<gc, block, lds_c, st>>>((const cx<float>*)in, in_row, in_batch, (cx<float>*)tmp, tmp_row,
-                                                  tmp_batch, ncols, p2, N1, lp, (const cx<float>*)tw2,
-                                                  (const cx<float>*)twN);
-        k_long_d<float><<<gd, block, lds_d, st>>>((const cx<float>*)tmp, tmp_row, tmp_batch, out, out_row, add,
-                                                  (float)add_scale, Nt, ncols, p1, N2, lp, (const cx<float>*)tw1,
-                                                  (float)out_scale);
+        with_sub_plan<float>(N2, [&](auto pl) {
+            k_long_c<float, decltype(pl)><<<gc, block, lds_c, st>>>(
+                (const cx<float>*)in, in_row, in_batch, (cx<float>*)tmp, tmp_row, tmp_batch, ncols, p2, N1, lp,
+                (const cx<float>*)tw2, (const cx<float>*)twN);
+        });
+        with_sub_plan<float>(N1, [&](auto pl) {
+            k_long_d<float, decltype(pl)><<<gd, block, lds_d, st>>>(
+                (const cx<float>*)tmp, tmp_row, tmp_batch, out, out_row, add, (float)add_scale, Nt, ncols, p1, N2,
+                lp, (const cx<float>*)tw1, (float)out_scale);
+        });
     } else {
-        k_long_c<double><<<gc, block, lds_c, st>>>((const cx<double>*)in, in_row, in_batch, (cx<double>*)tmp,
-                                                   tmp_row, tmp_batch, ncols, p2, N1, lp, (const cx<double>*)tw2,
-                                                   (const cx<double>*)twN);
-        k_long_d<double><<<gd, block, lds_d, st>>>((const cx<double>*)tmp, tmp_row, tmp_batch, out, out_row, add,
-                                                   add_scale, Nt, ncols, p1, N2, lp, (const cx<double>*)tw1,
-                                                   out_scale);
+        with_sub_plan<double>(N2, [&](auto pl) {
+            k_long_c<double, decltype(pl)><<<gc, block, lds_c, st>>>(
+                (const cx<double>*)in, in_row, in_batch, (cx<double>*)tmp, tmp_row, tmp_batch, ncols, p2, N1, lp,
+                (const cx<double>*)tw2, (const cx<double>*)twN);
+        });
+        with_sub_plan<double>(N1, [&](auto pl) {
+            k_long_d<double, decltype(pl)><<<gd, block, lds_d, st>>>(
+                (const cx<double>*)tmp, tmp_row, tmp_batch, out, out_row, add, add_scale, Nt, ncols, p1, N2, lp,
+                (const cx<double>*)tw1, out_scale);
+        });
     }
     return hipGetLastError();
 }
