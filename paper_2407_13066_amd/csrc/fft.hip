@@ -816,15 +816,25 @@ typedef CtPlan<8, 5, 5, 5, 4> Plan4000df;
     X(0, Plan420f)                \
     X(1, Plan1000d)               \
     X(2, Plan2000df)              \
-    X(3, Plan4000df)
+    X(3, Plan4000df)              \
+    X(4, Plan32)                  \
+    X(5, Plan64)                  \
+    X(6, Plan128f)                \
+    X(7, Plan256f)                \
+    X(8, Plan512)
 
-// FP64 transforms (double registers: plans of radix at most 16), for the benchmarked lengths
-// N = 420, 1000, 2000 and 4000.
+// FP64 transforms (double registers: plans of radix at most 16 where they do not spill), for the
+// benchmarked lengths N = 32 .. 512, 420, 1000, 2000 and 4000.
 #define BT_STATIC_PLANS64(X) \
     X(0, Plan420f)           \
     X(1, Plan1000d)          \
     X(2, Plan2000d)          \
-    X(3, Plan4000d)
+    X(3, Plan4000d)          \
+    X(4, Plan32)             \
+    X(5, Plan64)             \
+    X(6, Plan128f)           \
+    X(7, Plan256f)           \
+    X(8, Plan512)
 
 // Index of the compile-time plan of `plan`'s length in the table of its precision, or -1; for
 // FP32 the same index selects the plan of that length in the vector-side or the fine table.
