@@ -43,7 +43,9 @@ def check(bt, blocks, storage, k, n1, seed, noise=2.0, prior=0.5):
 
 # (Nt, Nd, Nm), k, n1: N = Nt (7-smooth) split as n1 x N/n1; ragged Nm and Nd, several tiles
 FORCED = [((32, 5, 300), 1, 4), ((32, 5, 300), 3, 8), ((60, 7, 1000), 2, 6), ((105, 3, 257), 1, 7),
-          ((128, 9, 700), 8, 16), ((420, 4, 130), 1, 20), ((420, 4, 130), 5, 21), ((48, 2, 33), 17, 6)]
+          ((128, 9, 700), 8, 16), ((420, 4, 130), 1, 20), ((420, 4, 130), 5, 21), ((48, 2, 33), 17, 6),
+          # sub-transforms with compile-time plans (100 x 100, 50 x 100, 100 x 50)
+          ((10000, 2, 37), 1, 100), ((5000, 3, 70), 2, 50), ((5000, 3, 70), 1, 100)]
 
 
 @pytest.mark.parametrize("shape,k,n1", FORCED)
