@@ -338,29 +338,44 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
     const int64_t frow = (int64_t)f * Nd;
     if (!BF) {
         const cx<float>* Fh = (const cx<float>*)Fh_;
-        // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs
-        for (int s0 = 0; s0 < Nd; s0 += 4) {
-            const int s = s0 + lg;
-            const bool sv = s < Nd;
-            const int sc = sv ? s : Nd - 1;
-            cx<float> b[2];
+        // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs.  The operator loads
+        // of the next kPre steps are in flight while a step runs.
+        constexpr int kPre = NT >= 4 ? 4 : 1;
+        uint2 ring[kPre][2];
+        auto loadB = [&](int s0, uint2(&dst)[2]) {
+            const int sc = min(s0 + lg, Nd - 1);
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const uint2 w = ld_nt8(Fh + (frow + sc) * ldF + pc[a]);
-                b[a] = sv ? cx<float>{__uint_as_float(w.x), __uint_as_float(w.y)} : cx<float>{0.f, 0.f};
-            }
+            for (int a = 0; a < 2; ++a) dst[a] = ld_nt8(Fh + (frow + sc) * ldF + pc[a]);
+        };
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
-                const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
-                const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
-                const bool imrow = li & 1;
-                const float a0 = imrow ? dim : dre;   // pairs with Re F
-                const float a1 = imrow ? -dre : dim;  // pairs with Im F
+        for (int j = 0; j < kPre; ++j)
+            if (4 * j < Nd) loadB(4 * j, ring[j]);
+        for (int sb = 0; sb < Nd; sb += 4 * kPre) {
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
-                    acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
+            for (int j = 0; j < kPre; ++j) {
+                const int s0 = sb + 4 * j;
+                if (s0 >= Nd) break;
+                const int s = s0 + lg;
+                const bool sv = s < Nd;
+                cx<float> b[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    b[a] = sv ? cx<float>{__uint_as_float(ring[j][a].x), __uint_as_float(ring[j][a].y)}
+                              : cx<float>{0.f, 0.f};
+                if (s0 + 4 * kPre < Nd) loadB(s0 + 4 * kPre, ring[j]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
+                    const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
+                    const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
+                    const bool imrow = li & 1;
+                    const float a0 = imrow ? dim : dre;   // pairs with Re F
+                    const float a1 = imrow ? -dre : dim;  // pairs with Im F
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
+                        acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
+                    }
                 }
             }
         }
