@@ -112,7 +112,7 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // with PAT, both B-operand patterns a lane can need (16 bytes, row stride kChunk + 1): lanes of
 // even result column (real part) take the first 8 bytes, lanes of odd column the second.
 template <bool BF, int NT, int kChunk>
-__global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
+__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
                                                            int64_t mh_batch, int nb, cx<float>* __restrict__ part,
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
@@ -129,17 +129,28 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
     const int nchunk = (ncol + kChunk - 1) / kChunk;
     const int rows_per_buf = NT * 8;
 
-    auto stage = [&](int c, int which) {
-        uint2* dst = buf + (size_t)which * rows_per_buf * LDR;
+    // Staging of a chunk of the vector side in two halves: the global loads of chunk c + 1 are
+    // issued into registers before chunk c is multiplied and written to LDS after it, so their
+    // latency is hidden behind the chunk's MFMAs.
+    constexpr int kPer = NT * 8 * kChunk / kGemmThreads;  // staged entries per thread
+    static_assert(kPer * kGemmThreads == NT * 8 * kChunk, "chunk entries split evenly over the threads");
+    auto stage_load = [&](int c, cx<float>* v) {
         const int cbase = col0 + c * kChunk;
-        for (int e = threadIdx.x; e < rows_per_buf * kChunk; e += kGemmThreads) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kGemmThreads;
             const int r = e / kChunk, q = e % kChunk;
-            float re = 0.f, im = 0.f;
-            if (r < nb && cbase + q < col0 + ncol) {
-                const cx<float> v = mh[(int64_t)r * mh_batch + (int64_t)f * ldv + cbase + q];
-                re = v.re;
-                im = v.im;
-            }
+            v[i] = cx<float>{0.f, 0.f};
+            if (r < nb && cbase + q < col0 + ncol) v[i] = mh[(int64_t)r * mh_batch + (int64_t)f * ldv + cbase + q];
+        }
+    };
+    auto stage_store = [&](int which, const cx<float>* v) {
+        uint2* dst = buf + (size_t)which * rows_per_buf * LDR;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kGemmThreads;
+            const int r = e / kChunk, q = e % kChunk;
+            const float re = v[i].re, im = v[i].im;
             if constexpr (PAT) {
                 // (pairs with Re F, pairs with Im F) for a real-part column, then for an
                 // imaginary-part column: (Re m, -Im m), (Im m, Re m)
@@ -177,11 +188,14 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
 
+        cx<float> sv[kPer];
         __syncthreads();
-        stage(0, 0);
+        stage_load(0, sv);
+        stage_store(0, sv);
         for (int c = 0; c < nchunk; ++c) {
+            // buffer c & 1 is complete, and every wave is done with buffer (c + 1) & 1
             __syncthreads();
-            if (c + 1 < nchunk) stage(c + 1, (c + 1) & 1);
+            if (c + 1 < nchunk) stage_load(c + 1, sv);
             const uint2* B = buf + (size_t)(c & 1) * rows_per_buf * LDR;
             const uint4* B4 = buf4 + (size_t)(c & 1) * rows_per_buf * LDR;
             const int cb = col0 + c * kChunk;  // first complex column of the chunk
@@ -269,6 +283,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_sbgemm_n(const void* __restric
                     }
                 }
             }
+            if (c + 1 < nchunk) stage_store((c + 1) & 1, sv);
         }
         // C[4 lg + v][li]: row s = rt0 + 16 a + 4 lg + v, column li -> rhs n*8 + li/2, part li&1
 #pragma unroll
