@@ -55,7 +55,27 @@ __global__ __launch_bounds__(kThreads64) void k_sbgemm_n64(const cx<double>* __r
     constexpr int rows_per_buf = NT * 8;
 
     typedef double d2v __attribute__((ext_vector_type(2)));
-    auto stage = [&](int c, int which) {
+    // Staging of a chunk of the vector side in two halves: with four tiles (where it costs no
+    // occupancy) the global loads of chunk c + 1 are issued into registers before chunk c is
+    // multiplied and written to LDS after it, so neither their latency nor a wait for them
+    // stalls the chunk's MFMAs; narrower tiles store them at once.
+    constexpr bool kSplit = NT >= 4;
+    constexpr int kPer = rows_per_buf * kChunk / kThreads64;  // staged entries per thread
+    static_assert(kPer * kThreads64 == rows_per_buf * kChunk, "chunk entries split evenly over the threads");
+    auto stage_load = [&](int c, d2v* v) {
+        const int cbase = col0 + c * kChunk;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kThreads64;
+            const int r = e / kChunk, q = e % kChunk;
+            const bool ok = r < nb && cbase + q < col0 + ncol;
+            const d2v* src = reinterpret_cast<const d2v*>(mh + (int64_t)min(r, nb - 1) * mh_batch + (int64_t)f * ldv +
+                                                          min(cbase + q, col0 + ncol - 1));
+            const d2v x = *src;
+            v[i] = ok ? x : d2v{0.0, 0.0};
+        }
+    };
+    auto stage = [&](int c, int which) {  // both halves at once, one entry at a time
         d2v* dst = reinterpret_cast<d2v*>(buf + (size_t)which * rows_per_buf * LDR);
         const int cbase = col0 + c * kChunk;
         for (int e = threadIdx.x; e < rows_per_buf * kChunk; e += kThreads64) {
@@ -65,6 +85,14 @@ __global__ __launch_bounds__(kThreads64) void k_sbgemm_n64(const cx<double>* __r
                                                           min(cbase + q, col0 + ncol - 1));
             const d2v v = *src;
             dst[r * LDR + q] = ok ? v : d2v{0.0, 0.0};
+        }
+    };
+    auto stage_store = [&](int which, const d2v* v) {
+        d2v* dst = reinterpret_cast<d2v*>(buf + (size_t)which * rows_per_buf * LDR);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kThreads64;
+            dst[(e / kChunk) * LDR + e % kChunk] = v[i];
         }
     };
     // Operator values of one K step (16 complex columns) for the wave's two row tiles: lane
@@ -96,42 +124,52 @@ __global__ __launch_bounds__(kThreads64) void k_sbgemm_n64(const cx<double>* __r
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[a][n] = d4v{0.0, 0.0, 0.0, 0.0};
 
+        d2v sv[kSplit ? kPer : 1];
         __syncthreads();
         stage(0, 0);
         // the next K step's operator loads are issued before the current step's MFMAs, also
         // across chunk boundaries (they do not depend on the staged vectors)
         if (t0) loadA(F0, F1, 0, 0, 0);
         for (int c = 0; c < nchunk; ++c) {
+            // buffer c & 1 is complete, and every wave is done with buffer (c + 1) & 1
             __syncthreads();
-            if (c + 1 < nchunk) stage(c + 1, (c + 1) & 1);
+            if (c + 1 < nchunk) {
+                if constexpr (kSplit)
+                    stage_load(c + 1, sv);
+                else
+                    stage(c + 1, (c + 1) & 1);
+            }
             const cx<double>* B = buf + (size_t)(c & 1) * rows_per_buf * LDR;
-            if (!t0) continue;
+            if (t0) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int cur = ks & 1;
-                if (ks + 1 < KS)
-                    loadA(F0, F1, c, ks + 1, cur ^ 1);
-                else if (c + 1 < nchunk)
-                    loadA(F0, F1, c + 1, 0, cur ^ 1);
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int cur = ks & 1;
+                    if (ks + 1 < KS)
+                        loadA(F0, F1, c, ks + 1, cur ^ 1);
+                    else if (c + 1 < nchunk)
+                        loadA(F0, F1, c + 1, 0, cur ^ 1);
 #pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const int r = n * 8 + (li >> 1);
-                    const bool imcol = li & 1;
+                    for (int n = 0; n < NT; ++n) {
+                        const int r = n * 8 + (li >> 1);
+                        const bool imcol = li & 1;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // K = (column 4 q + lg, part): pairs with Re F and with Im F
-                        const cx<double> mv = B[r * LDR + ks * 16 + 4 * q + lg];
-                        const double b0 = imcol ? mv.im : mv.re;
-                        const double b1 = imcol ? mv.re : -mv.im;
-                        acc[0][n] = mfma_f64(A0[cur][q].re, b0, acc[0][n]);
-                        acc[0][n] = mfma_f64(A0[cur][q].im, b1, acc[0][n]);
-                        if (t1) {
-                            acc[1][n] = mfma_f64(A1[cur][q].re, b0, acc[1][n]);
-                            acc[1][n] = mfma_f64(A1[cur][q].im, b1, acc[1][n]);
+                        for (int q = 0; q < 4; ++q) {
+                            // K = (column 4 q + lg, part): pairs with Re F and with Im F
+                            const cx<double> mv = B[r * LDR + ks * 16 + 4 * q + lg];
+                            const double b0 = imcol ? mv.im : mv.re;
+                            const double b1 = imcol ? mv.re : -mv.im;
+                            acc[0][n] = mfma_f64(A0[cur][q].re, b0, acc[0][n]);
+                            acc[0][n] = mfma_f64(A0[cur][q].im, b1, acc[0][n]);
+                            if (t1) {
+                                acc[1][n] = mfma_f64(A1[cur][q].re, b0, acc[1][n]);
+                                acc[1][n] = mfma_f64(A1[cur][q].im, b1, acc[1][n]);
+                            }
                         }
                     }
                 }
             }
+            if constexpr (kSplit)
+                if (c + 1 < nchunk) stage_store((c + 1) & 1, sv);
         }
         // C[lg + 4 v][li]: row s = rt0 + 16 a + lg + 4 v, column li -> rhs n*8 + li/2, part li&1
 #pragma unroll
