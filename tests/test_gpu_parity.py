@@ -153,6 +153,29 @@ def test_multi_rhs_matrix_cores(bt, shape, k, storage):
         assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol, ("H", r)
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_multi_rhs_on_a_wide_launch(bt, storage):
+    """Enough (span, frequency) workgroups (66 x 65) for the forward product's wide chunks of
+    vector columns, with a ragged last span (Nm = 65 x 4096 + 3761)."""
+    Nt, Nd, Nm, k = 64, 3, 270001, 8
+    print("wide multi", storage, flush=True)
+    blocks = synth.blocks(Nt, Nd, Nm, tau=Nt / 6, seed=111)
+    op = make(bt, blocks, storage)
+    M = synth.vectors(k, Nt, Nm, stream=112)
+    Md = to_dev(M, op.vector_dtype)
+    M64 = Md.double().cpu().numpy()  # the vectors as the device holds them
+    FM = bt.btoep_apply_F(op, Md).double().cpu().numpy()
+    HM = bt.btoep_apply_H(op, Md, 1.5, 0.75).double().cpu().numpy()
+    FM_ref = oracle.apply_F(blocks, M64)
+    HM_ref = oracle.apply_H(blocks, M64[[0, 5]], 1.5, 0.75)
+    tol = TOL[storage]
+    for r in range(k):
+        assert oracle.rel_l2(FM[r], FM_ref[r]) <= tol, ("F", r)
+    for i, r in enumerate((0, 5)):
+        assert oracle.rel_l2(HM[r], HM_ref[i]) <= tol, ("H", r)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_matrix_core_results_are_batch_invariant(bt, storage):
     """A right-hand side gives bitwise the same result in any batch of k >= 2 and at any position."""
