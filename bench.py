@@ -489,7 +489,7 @@ def main():
                     help="parameter columns of the operator the CPU oracle is timed on")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (use --gpus 1)",
               file=sys.stderr)
         return 2
 
