@@ -106,6 +106,12 @@ def load_library(path=LIB_PATH):
         "btoep_cg_status": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], st),
         "btoep_cg_end": ([vp], st),
+        "btoep_cg_state_size": ([vp, vp, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)], st),
+        "btoep_cg_begin": ([vp, vp, i64, vp, vp, dbl, dbl, vp, sz, vp, sz, vp, ctypes.POINTER(vp)], st),
+        "btoep_cg_residual_vectors": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp)], st),
+        "btoep_cg_refine": ([vp, vp], st),
+        "btoep_cg_report": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(CgResult)], st),
+        "btoep_cg_workspace_size": ([vp, vp, i64, ctypes.POINTER(sz)], st),
         "btoep_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "btoep_last_error": ([vp], ctypes.c_char_p),
     }
@@ -297,15 +303,34 @@ def btoep_workspace_size(op, which, k=1):
     return n.value
 
 
-def _vec(op, t, tail, name):
+def _vec(op, t, tail, name, dtype=None, single=False):
+    """Check a vector argument: a contiguous CUDA tensor on the operator's device, of the
+    operator's vector dtype (or ``dtype``), shaped [k]+tail (or tail, read as k = 1; only
+    tail when ``single``).  Returns the [k]+tail view."""
     torch = _torch()
-    if not t.is_cuda or t.dtype != op.vector_dtype or not t.is_contiguous():
-        raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, op.vector_dtype))
-    if t.dim() == 2:
-        t = t.unsqueeze(0)
-    if t.dim() != 3 or tuple(t.shape[1:]) != tail:
-        raise ValueError("%s has shape %s, expected [k]%s" % (name, tuple(t.shape), list(tail)))
-    return t
+    dtype = op.vector_dtype if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    t3 = t.unsqueeze(0) if t.dim() == 2 else t
+    if t3.dim() != 3 or tuple(t3.shape[1:]) != tuple(tail) or (single and t3.shape[0] != 1):
+        raise ValueError("%s has shape %s, expected %s%s" % (name, tuple(t.shape), "" if single else "[k]",
+                                                             list(tail)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.device.index != op.info["device"]:
+        raise ValueError("%s is on cuda:%s, the operator on cuda:%d" % (name, t.device.index, op.info["device"]))
+    return t3
+
+
+def _io_tails(op, which):
+    """Trailing shapes of the input and output vectors of an apply."""
+    n_in = op.Nd if which == "FT" else op.Nm
+    n_out = op.Nd if which == "F" else op.Nm
+    return (op.Nt, n_in), (op.Nt, n_out)
 
 
 def _ws(ws):
@@ -368,6 +393,12 @@ def btoep_apply_batched(op, which, ins, outs, noise_prec=1.0, prior_prec=1.0, ws
     k = len(ins)
     if k != len(outs) or k > MAX_BATCH:
         raise ValueError("need len(ins) == len(outs) <= %d" % MAX_BATCH)
+    if which not in ("F", "FT", "H"):
+        raise ValueError("which must be 'F', 'FT' or 'H'")
+    tin, tout = _io_tails(op, which)
+    for r in range(k):
+        _vec(op, ins[r], tin, "ins[%d]" % r, single=True)
+        _vec(op, outs[r], tout, "outs[%d]" % r, single=True)
     PA = ctypes.c_void_p * max(k, 1)
     pin = PA(*[t.data_ptr() for t in ins])
     pout = PA(*[t.data_ptr() for t in outs])
@@ -387,10 +418,11 @@ def btoep_cg_solve(op_lo, op_hi, b, x, noise_prec, prior_prec, rtol=1e-8, max_ou
     Returns (status, [CgResult per right-hand side]).
     """
     torch = _torch()
-    for t, n in ((b, "b"), (x, "x")):
-        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-            raise ValueError("%s must be a contiguous float64 CUDA tensor" % n)
-    b3 = b if b.dim() == 3 else b.unsqueeze(0)
+    tail = (op_lo.Nt, op_lo.Nm)
+    if tuple(x.shape) != tuple(b.shape):
+        raise ValueError("x has shape %s, b %s: they must match" % (tuple(x.shape), tuple(b.shape)))
+    b3 = _vec(op_lo, b, tail, "b", dtype=torch.float64)
+    _vec(op_lo, x, tail, "x", dtype=torch.float64)
     k = b3.shape[0]
     opts = CgOpts(rtol, max_outer, max_inner, inner_rtol, check_every, 1 if use_graph else 0)
     res = (CgResult * k)()
@@ -445,21 +477,39 @@ def btoep_set_tuning(op, var_n, var_c, use_mfma=True):
 
 
 class CgState:
-    """Stepwise CG on one operator (btoep_cg_*): the caller applies H to ``p`` into ``Ap``."""
+    """Stepwise CG (btoep_cg_*): the caller applies H_lo to ``p`` into ``Ap`` before each
+    update and, with a refinement operator, H_hi to ``x`` into ``Hx`` before each refine.
 
-    def __init__(self, op, handle, k):
-        self.op, self.handle, self.k = op, handle, k
+    ``keep`` holds the caller-side memory (device and pinned host tensors) of a state made by
+    btoep_cg_begin, so that it lives as long as the state."""
+
+    def __init__(self, op, handle, k, op_hi=None, keep=None):
+        self.op, self.op_hi, self.handle, self.k, self.keep = op, op_hi, handle, k, keep
         p, ap = ctypes.c_void_p(), ctypes.c_void_p()
         _check(load_library().btoep_cg_vectors(handle, ctypes.byref(p), ctypes.byref(ap)), "btoep_cg_vectors",
                op.handle)
         self.p_ptr, self.ap_ptr = p.value, ap.value
         self.vec_bytes = op.Nt * op.Nm * (8 if op.storage == "f64" else 4)
+        self.x_ptr = self.hx_ptr = None
+        if op_hi is not None:
+            x, hx = ctypes.c_void_p(), ctypes.c_void_p()
+            _check(load_library().btoep_cg_residual_vectors(handle, ctypes.byref(x), ctypes.byref(hx)),
+                   "btoep_cg_residual_vectors", op.handle)
+            self.x_ptr, self.hx_ptr = x.value, hx.value
 
     def p(self, r):
         return self.p_ptr + r * self.vec_bytes
 
     def ap(self, r):
         return self.ap_ptr + r * self.vec_bytes
+
+    def x(self, r):
+        """FP64 iterate of right-hand side r (refined state only)."""
+        return self.x_ptr + r * self.op.Nt * self.op.Nm * 8
+
+    def hx(self, r):
+        """FP64 array that receives H_hi x of right-hand side r (refined state only)."""
+        return self.hx_ptr + r * self.op.Nt * self.op.Nm * 8
 
     def tensors(self):
         """Torch views [k][Nt][Nm] of the state's p and Ap arrays (device memory the state owns;
@@ -497,6 +547,66 @@ def btoep_cg_start(op, b, x, rtol, noise_prec=1.0, prior_prec=1.0, stream=None):
                                          ctypes.c_void_p(b3.data_ptr()), ctypes.c_void_p(x3.data_ptr()),
                                          float(rtol), _stream(stream), ctypes.byref(h)), "btoep_cg_start", op.handle)
     return CgState(op, h, b3.shape[0])
+
+
+def btoep_cg_state_size(op_lo, op_hi, k):
+    """(device bytes, pinned host bytes) of a stepwise CG state for k right-hand sides."""
+    dev, host = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().btoep_cg_state_size(op_lo.handle, op_hi.handle if op_hi is not None else None, int(k),
+                                              ctypes.byref(dev), ctypes.byref(host)),
+           "btoep_cg_state_size", op_lo.handle)
+    return dev.value, host.value
+
+
+def btoep_cg_begin(op_lo, op_hi, b, x, rtol, inner_rtol, dev_mem, host_mem, stream=None):
+    """Stepwise CG on caller memory (no allocation, no synchronisation).
+
+    b, x : [k][Nt][Nm], float64 with a refinement operator ``op_hi``, else op_lo's vector type.
+    dev_mem : uint8 CUDA tensor, host_mem : pinned uint8 CPU tensor, at least
+    btoep_cg_state_size bytes each; kept alive by the returned state."""
+    torch = _torch()
+    vt = torch.float64 if op_hi is not None else op_lo.vector_dtype
+    b3 = _vec(op_lo, b, (op_lo.Nt, op_lo.Nm), "b", dtype=vt)
+    x3 = _vec(op_lo, x, (op_lo.Nt, op_lo.Nm), "x", dtype=vt)
+    if x3.shape != b3.shape:
+        raise ValueError("x and b must have the same shape")
+    if not dev_mem.is_cuda or not dev_mem.is_contiguous():
+        raise ValueError("dev_mem must be a contiguous CUDA tensor")
+    if host_mem.is_cuda or not host_mem.is_pinned():
+        raise ValueError("host_mem must be pinned host memory")
+    h = ctypes.c_void_p()
+    _check(load_library().btoep_cg_begin(
+        op_lo.handle, op_hi.handle if op_hi is not None else None, b3.shape[0], ctypes.c_void_p(b3.data_ptr()),
+        ctypes.c_void_p(x3.data_ptr()), float(rtol), float(inner_rtol), ctypes.c_void_p(dev_mem.data_ptr()),
+        dev_mem.numel() * dev_mem.element_size(), ctypes.c_void_p(host_mem.data_ptr()),
+        host_mem.numel() * host_mem.element_size(), _stream(stream), ctypes.byref(h)), "btoep_cg_begin",
+        op_lo.handle)
+    return CgState(op_lo, h, b3.shape[0], op_hi=op_hi, keep=(dev_mem, host_mem, b, x))
+
+
+def btoep_cg_refine(cg, stream=None):
+    """After Hx = H_hi x: true residual in FP64, outer test, restart of the inner iteration."""
+    _check(load_library().btoep_cg_refine(cg.handle, _stream(stream)), "btoep_cg_refine", cg.op.handle)
+
+
+def btoep_cg_report(cg):
+    """(ready, [per right-hand side dict]) of the last landed poll -- never blocks."""
+    ready = ctypes.c_int()
+    res = (CgResult * cg.k)()
+    _check(load_library().btoep_cg_report(cg.handle, ctypes.byref(ready), res), "btoep_cg_report", cg.op.handle)
+    if not ready.value:
+        return False, None
+    return True, [dict(inner_iters=r.inner_iters, outer_iters=r.outer_iters, matvecs=r.matvecs,
+                       converged=bool(r.converged), rel_residual=r.rel_residual) for r in res]
+
+
+def btoep_cg_workspace_size(op_lo, op_hi, k=1):
+    """Workspace bytes of btoep_cg_solve(op_lo, op_hi, k)."""
+    n = ctypes.c_size_t()
+    _check(load_library().btoep_cg_workspace_size(op_lo.handle, op_hi.handle if op_hi is not None else None,
+                                                  int(k), ctypes.byref(n)), "btoep_cg_workspace_size",
+           op_lo.handle)
+    return n.value
 
 
 def btoep_cg_update(cg, stream=None):

@@ -8,7 +8,7 @@
 //                Lanes walk p; each workgroup owns one frequency and a span of CS columns
 //                (its slice of mh_f staged in LDS) and every wave reduces RB rows at a time
 //                across its 64 lanes.  The per-span results are written as partial sums
-//                part[f][span][s]; the data-side kernel adds them in a fixed order, so the
+//                part[b][s][f][span]; the data-side kernel adds them in a fixed order, so the
 //                result is deterministic (no floating-point atomics).
 //   C (for F^T): mo_f[p] = sum_s conj(Fh_f[s][p]) dh_f[s]   (paper section 3.4, eq. AdjointFFTMatvec)
 //                Lanes own p and loop over s with dh_f broadcast from LDS: no reduction.

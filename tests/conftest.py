@@ -15,10 +15,10 @@ import pytest  # noqa: E402
 
 @pytest.fixture(scope="session")
 def bt():
-    """The HIP binding; builds libbtoep.so only when no library is present."""
+    """The HIP binding; (re)builds libbtoep.so when it is missing or older than a source."""
     import paper_2407_13066_amd as pkg
     from paper_2407_13066_amd import build
-    if not os.path.exists(pkg.LIB_PATH):
+    if build.stale():
         build.build()
     pkg.load_library()
     return pkg

@@ -190,3 +190,78 @@ def test_golden_fp64_small():
         idx = np.array(ent["index"])
         np.testing.assert_allclose(v[idx], np.array(ent["value"]), rtol=1e-13, atol=1e-13)
         assert abs(np.linalg.norm(v) - ent["norm"]) <= 1e-12 * ent["norm"]
+
+
+# ---- the dense assembler ------------------------------------------------------------
+# oracle.dense_F assembles the block matrix of eq. ShiftInvariance (section 2.1): block row i,
+# block column j holds F_{i-j} for i >= j and zero above the block diagonal.  It is pinned to
+# facts that do not go through the oracle's own code: scipy's Toeplitz constructor for
+# Nd = Nm = 1, time stepping of an LTI system (section 2.1), the entry-by-entry assembly in
+# tests/pins.py, and the delta property (block column 0 is the first block column).
+
+def _dense_pins(dense):
+    """Worst relative error of ``dense`` over every pin of the assembler."""
+    import scipy.linalg
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for Nt in (1, 2, 5, 9):
+        f = rng.standard_normal(Nt)
+        T = scipy.linalg.toeplitz(f, np.zeros(Nt))      # lower-triangular Toeplitz
+        worst = max(worst, pins.rel(dense(f.reshape(Nt, 1, 1)), T))
+    for (Nt, Nd, Nm) in pins.TINY_SHAPES:
+        blocks = rng.standard_normal((Nt, Nd, Nm))
+        A = dense(blocks)
+        if A.shape != (Nt * Nd, Nt * Nm):
+            return np.inf
+        worst = max(worst, pins.rel(A, pins.dense_matrix(blocks)))
+        # block column 0 is the first block column, stacked over block rows
+        worst = max(worst, pins.rel(A[:, :Nm], blocks.reshape(Nt * Nd, Nm)))
+    A_, B, C, blocks = pins.lti_system(rng, 7, 3, 4, 10)
+    m = rng.standard_normal((10, 4))
+    u = np.zeros(7)
+    d = np.empty((10, 3))
+    for k in range(10):
+        u = A_ @ u + C @ m[k]
+        d[k] = B @ u
+    worst = max(worst, pins.rel(dense(blocks) @ m.ravel(), d.ravel()))
+    return worst
+
+
+def test_dense_assembler_pinned():
+    assert _dense_pins(oracle.dense_F) < 1e-14
+
+
+def _dense_mutant_upper(blocks):
+    # the triangle mirrored: F_{j-i} placed where j >= i
+    Nt, Nd, Nm = blocks.shape
+    A = np.zeros((Nt * Nd, Nt * Nm))
+    for i in range(Nt):
+        for j in range(Nt):
+            if i <= j:
+                A[i * Nd:(i + 1) * Nd, j * Nm:(j + 1) * Nm] = blocks[j - i]
+    return A
+
+
+def _dense_mutant_strict(blocks):
+    # diagonal blocks dropped (i > j instead of i >= j)
+    Nt, Nd, Nm = blocks.shape
+    A = np.zeros((Nt * Nd, Nt * Nm))
+    for i in range(Nt):
+        for j in range(i):
+            A[i * Nd:(i + 1) * Nd, j * Nm:(j + 1) * Nm] = blocks[i - j]
+    return A
+
+
+def _dense_mutant_lag(blocks):
+    # block (i, j) takes F_{i-j-1}: the block column shifted down one block
+    Nt, Nd, Nm = blocks.shape
+    A = np.zeros((Nt * Nd, Nt * Nm))
+    for i in range(Nt):
+        for j in range(i):
+            A[i * Nd:(i + 1) * Nd, j * Nm:(j + 1) * Nm] = blocks[i - j - 1]
+    return A
+
+
+@pytest.mark.parametrize("dense", [_dense_mutant_upper, _dense_mutant_strict, _dense_mutant_lag])
+def test_dense_assembler_pins_catch_planted_mistakes(dense):
+    assert _dense_pins(dense) > 1e-6
