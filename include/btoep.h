@@ -211,7 +211,8 @@ btoep_status btoep_apply_batched(btoep_op op, btoep_which which, int64_t k, cons
  * them from a device table the graph owns, which btoep_graph_launch rewrites (with a small
  * kernel on `stream`, right before the replay) from
  *   in[r], out[r]  (HOST arrays of k device pointers, as for btoep_apply_batched; both NULL
- *                   to replay on the previous launch's vectors).
+ *                   to replay on the previous launch's vectors -- INVALID_ARG, with nothing
+ *                   launched, before any launch has given vectors).
  * For _H no output may overlap an input.  `ws` (caller owned, at least
  * btoep_workspace_size(op, which, k) bytes, required) and the operator are used by every
  * replay and must outlive the graph.  Launches of one graph must be ordered on one stream
@@ -253,8 +254,10 @@ typedef struct {
  *   b, x : FP64 device arrays [k][Nt][Nm]; x holds the initial guess and receives x.
  *   results : HOST array of k entries (may be NULL).
  * Returns BTOEP_ERR_NOT_CONVERGED (x still written) when some right-hand side missed rtol.
- * op_lo and op_hi must have the same Nt, Nd, Nm and device.
+ * op_lo and op_hi must have the same Nt, Nd, Nm and device.  The workspace needs at least
+ * btoep_cg_workspace_size(op_lo, op_hi, k) bytes.
  */
+btoep_status btoep_cg_workspace_size(btoep_op op_lo, btoep_op op_hi, int64_t k, size_t* bytes);
 btoep_status btoep_cg_solve(btoep_op op_lo, btoep_op op_hi, int64_t k, double noise_prec, double prior_prec,
                             const double* b, double* x, const btoep_cg_opts* opts, btoep_cg_result* results,
                             void* ws, size_t ws_bytes, void* stream);
@@ -327,17 +330,56 @@ btoep_status btoep_profile_read(btoep_op op, btoep_kernel_time* out, int max, in
  *   btoep_cg_status  : non-blocking; ready = 1 once the last poll landed, then active =
  *                      right-hand sides still iterating, iters = largest iteration count,
  *                      rel_res (host [k], may be NULL) = ||r|| / ||b|| per right-hand side.
- *   btoep_cg_end     : releases the state (synchronises the device).
+ *   btoep_cg_end     : releases the state; a state from btoep_cg_start frees its memory
+ *                      (synchronises the device), one from btoep_cg_begin only its host
+ *                      object (no device call that waits).
  * All calls on one state must be ordered on one stream.
+ *
+ * Refined stepwise CG on caller memory, for servers that must neither allocate nor wait
+ * (section 2.2 with the FP64 refinement of btoep_cg_solve):
+ *   btoep_cg_state_size : device and pinned-host bytes of a state for k right-hand sides.
+ *   btoep_cg_begin : like btoep_cg_start, but the state lives in `dev_mem` (device, 256-byte
+ *                    aligned) and `host_mem` (pinned host memory), both caller owned and at
+ *                    least btoep_cg_state_size bytes; it allocates no device memory and
+ *                    launches only kernels on `stream`.  With op_hi (an FP64 operator of the
+ *                    same shape; op_hi may be op_lo itself when that is FP64), b and x are
+ *                    FP64 and the solve is refined: the inner iteration on op_lo's vectors
+ *                    stops once its recurrence residual has dropped by inner_rtol (0 < inner_rtol
+ *                    < 1), or below rtol/2 relative to b, and the caller then applies H_hi to x
+ *                    (btoep_cg_residual_vectors: x, and the FP64 array Hx that receives H_hi x)
+ *                    and calls btoep_cg_refine.  Without op_hi, b and x have op_lo's vector type
+ *                    and the state behaves as one from btoep_cg_start (inner_rtol unused).
+ *                    x is set to 0.  The memory may be reused once all work enqueued on the
+ *                    state has completed.
+ *   btoep_cg_update  : also accumulates x (FP64 when refined) += alpha p.
+ *   btoep_cg_refine  : after Hx = H_hi x: the true residual b - H_hi x in FP64, the outer test
+ *                      ||b - H_hi x|| <= rtol ||b||, and a restart of the inner iteration on that
+ *                      residual for the right-hand sides that missed it (INVALID_ARG unrefined).
+ *   btoep_cg_report  : non-blocking; ready = 1 once the last poll landed, then per right-hand
+ *                      side (HOST array of k): inner iterations, refinement steps, H
+ *                      applications (updates + refinements), converged and rel_residual -- the
+ *                      true FP64 residual of the last refinement when refined (the x = 0 one
+ *                      before the first), else the recurrence residual.
+ * Errors: INVALID_ARG (null pointers, k outside 1..BTOEP_MAX_BATCH, rtol <= 0, operators that
+ * differ in shape or device, a non-FP64 op_hi, misaligned memory), WORKSPACE_TOO_SMALL (memory
+ * smaller than btoep_cg_state_size), HIP.
  */
 typedef struct btoep_cg_s* btoep_cg;
 
 btoep_status btoep_cg_start(btoep_op op, int64_t k, double noise_prec, double prior_prec, const void* b, void* x,
                             double rtol, void* stream, btoep_cg* out);
+btoep_status btoep_cg_state_size(btoep_op op_lo, btoep_op op_hi, int64_t k, size_t* dev_bytes,
+                                 size_t* host_bytes);
+btoep_status btoep_cg_begin(btoep_op op_lo, btoep_op op_hi, int64_t k, const void* b, void* x, double rtol,
+                            double inner_rtol, void* dev_mem, size_t dev_bytes, void* host_mem, size_t host_bytes,
+                            void* stream, btoep_cg* out);
 btoep_status btoep_cg_vectors(btoep_cg cg, void** p, void** Ap);
+btoep_status btoep_cg_residual_vectors(btoep_cg cg, void** x, void** Hx);
 btoep_status btoep_cg_update(btoep_cg cg, void* stream);
+btoep_status btoep_cg_refine(btoep_cg cg, void* stream);
 btoep_status btoep_cg_poll(btoep_cg cg, void* stream);
 btoep_status btoep_cg_status(btoep_cg cg, int* ready, int* active, int* iters, double* rel_res);
+btoep_status btoep_cg_report(btoep_cg cg, int* ready, btoep_cg_result* results);
 btoep_status btoep_cg_end(btoep_cg cg);
 
 /* Static text for a status code. */

@@ -945,6 +945,7 @@ struct btoep_graph_s {
     btoep_op op = nullptr;
     int k = 0;
     const void** table = nullptr;  // device: k input addresses, then k output addresses
+    bool table_set = false;        // a launch has written the table
     GraphHolder h;
     ~btoep_graph_s() {
         if (table) (void)hipFree(table);
@@ -1000,6 +1001,7 @@ btoep_status btoep_graph_create(btoep_op op, btoep_which which, int64_t k, doubl
 
 btoep_status btoep_graph_launch(btoep_graph gr, const void* const* in, void* const* out, void* stream) {
     if (!gr || (!in) != (!out)) return BTOEP_ERR_INVALID_ARG;
+    if (!in && !gr->table_set) return BTOEP_ERR_INVALID_ARG;  // no vectors to replay on yet
     hipStream_t st = (hipStream_t)stream;
     DeviceGuard g(gr->op->device);
     if (in) {
@@ -1011,6 +1013,7 @@ btoep_status btoep_graph_launch(btoep_graph gr, const void* const* in, void* con
         }
         k_write_table<<<1, kMaxBatch, 0, st>>>(pi, po, gr->k, gr->table);
         BT_HIP(gr->op, hipGetLastError());
+        gr->table_set = true;
     }
     BT_HIP(gr->op, hipGraphLaunch(gr->h.x, st));
     return BTOEP_OK;
@@ -1107,7 +1110,7 @@ btoep_status btoep_cg_solve(btoep_op lo, btoep_op hi, int64_t k, double noise_pr
         BT_HIP(lo, launch_axpbz(rl, e, 0.0, rl, r, 0.0, rl, nullptr, n, nb, n, st));
         BT_HIP(lo, launch_axpbz(rl, p, 1.0, rl, r, 0.0, rl, nullptr, n, nb, n, st));
         BT_HIP(lo, launch_dot(rl, r, r, n, nb, n, sc, kScRR, 0, tmp, st));
-        BT_HIP(lo, launch_cg_init_scalars(sc, nb, o.inner_rtol * o.inner_rtol, rtol2, st));
+        BT_HIP(lo, launch_cg_init_scalars(sc, nb, o.inner_rtol * o.inner_rtol, rtol2, 0.0, st));
         if (o.use_graph && !step.x) {
             s = capture_graph(lo, step, inner_step);
             if (s != BTOEP_OK) return s;
@@ -1381,31 +1384,170 @@ btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma) {
 
 }  // extern "C"
 
+// ---- stepwise CG ----------------------------------------------------------------------
+// State of one stepwise solve.  The caller applies H_lo p (and, with a refinement operator,
+// H_hi x); the state holds the CG vectors in the inner operator's vector type, the FP64
+// scalars and, when refined, the FP64 array that receives H_hi x and becomes the residual.
 struct btoep_cg_s {
-    btoep_op op = nullptr;
+    btoep_op op = nullptr;  // inner operator
+    btoep_op hi = nullptr;  // FP64 refinement operator, or null
     int64_t k = 0, n = 0;
+    const void* b = nullptr;
     void* x = nullptr;
     void* r = nullptr;
     void* p = nullptr;
     void* Ap = nullptr;
+    double* hx = nullptr;
     double* sc = nullptr;
     double* tmp = nullptr;
     double* host = nullptr;  // pinned copy of the scalars
+    void* owned_dev = nullptr;  // memory allocated by btoep_cg_start (null for btoep_cg_begin)
+    bool owned_host = false;
     hipEvent_t ev = nullptr;
     bool polled = false;
+    double rtol2 = 0.0, inner_rtol2 = 0.0;
+    int outer = 0, updates = 0;           // refinement steps and updates enqueued so far
+    int seen_outer = 0, seen_updates = 0;  // the same, as of the last poll
 };
+
+namespace {
+
+// Offsets of the state's arrays in its device memory.
+struct CgStateLayout {
+    size_t sc = 0, tmp = 0, r = 0, p = 0, Ap = 0, hx = 0, total = 0, host = 0;
+};
+CgStateLayout cg_state_layout(const btoep_op lo, const btoep_op hi, int64_t k) {
+    const size_t n = (size_t)lo->Nt * lo->Nm, vl = vbytes(lo);
+    CgStateLayout w;
+    size_t off = 0;
+    auto put = [&](size_t& slot, size_t bytes) {
+        slot = off;
+        off += align_up(bytes, 256);
+    };
+    put(w.sc, (size_t)k * kScal * sizeof(double));
+    put(w.tmp, dot_tmp_doubles((int)k) * sizeof(double));
+    put(w.r, (size_t)k * n * vl);
+    put(w.p, (size_t)k * n * vl);
+    put(w.Ap, (size_t)k * n * vl);
+    if (hi) put(w.hx, (size_t)k * n * sizeof(double));
+    w.total = off;
+    w.host = (size_t)k * kScal * sizeof(double);
+    return w;
+}
+
+bool cg_pair_ok(const btoep_op lo, const btoep_op hi) {
+    return !hi || (hi->storage == BTOEP_F64 && hi->Nt == lo->Nt && hi->Nd == lo->Nd && hi->Nm == lo->Nm &&
+                   hi->device == lo->device);
+}
+
+// Restart of the inner iteration from the residual held in `res` (type rres): r = res,
+// p = r, RR = <r, r>, thresholds and active flags.
+hipError_t cg_restart(btoep_cg cg, const void* res, Real rres, double outer_rtol2, double floor2, hipStream_t st) {
+    const Real rv = cg->op->vreal;
+    const int nb = (int)cg->k;
+    const int64_t n = cg->n;
+    hipError_t e = launch_axpbz(rv, cg->r, 1.0, rres, res, 0.0, rres, nullptr, n, nb, n, st);
+    if (e == hipSuccess) e = launch_axpbz(rv, cg->p, 1.0, rv, cg->r, 0.0, rv, nullptr, n, nb, n, st);
+    if (e == hipSuccess) e = launch_dot(rv, cg->r, cg->r, n, nb, n, cg->sc, kScRR, 0, cg->tmp, st);
+    if (e == hipSuccess) e = launch_cg_init_scalars(cg->sc, nb, cg->inner_rtol2, outer_rtol2, floor2, st);
+    return e;
+}
+
+// Initial state: x = 0, so the true residual is b itself.  Refined: BB = RH = <b, b> in FP64,
+// inner iteration on r = b rounded to the inner type.  Plain: the recurrence residual is the
+// only one and the inner threshold is rtol itself.
+hipError_t cg_init(btoep_cg cg, hipStream_t st) {
+    const btoep_op op = cg->op;
+    const int nb = (int)cg->k;
+    const int64_t n = cg->n;
+    const Real rb = cg->hi ? Real::F64 : op->vreal;  // type of b and x
+    hipError_t e = launch_zero(Real::F64, cg->sc, (int64_t)nb * kScal, st);
+    if (e == hipSuccess) e = launch_zero(rb, cg->x, (int64_t)nb * n, st);
+    if (e == hipSuccess) e = launch_dot(rb, cg->b, cg->b, n, nb, n, cg->sc, kScBB, 0, cg->tmp, st);
+    if (e == hipSuccess) e = launch_dot(rb, cg->b, cg->b, n, nb, n, cg->sc, kScRH, 0, cg->tmp, st);
+    if (e != hipSuccess) return e;
+    if (cg->hi) return cg_restart(cg, cg->b, Real::F64, cg->rtol2, 0.25 * cg->rtol2, st);
+    // plain: stop on ||r||^2 <= rtol^2 ||b||^2; outer test 0 keeps every nonzero column active
+    cg->inner_rtol2 = cg->rtol2;
+    return cg_restart(cg, cg->b, rb, 0.0, 0.0, st);
+}
+
+void cg_free(btoep_cg cg) {
+    if (cg->ev) (void)hipEventDestroy(cg->ev);
+    if (cg->owned_dev) (void)hipFree(cg->owned_dev);
+    if (cg->owned_host && cg->host) (void)hipHostFree(cg->host);
+    delete cg;
+}
+
+btoep_status cg_err(btoep_op op, const char* what, hipError_t e) {
+    set_err(op, what, e);
+    return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+}
+
+// Points the state's arrays into `dev` (laid out by cg_state_layout) and `host`.
+void cg_bind(btoep_cg cg, const CgStateLayout& w, char* dev, double* host) {
+    cg->sc = (double*)(dev + w.sc);
+    cg->tmp = (double*)(dev + w.tmp);
+    cg->r = dev + w.r;
+    cg->p = dev + w.p;
+    cg->Ap = dev + w.Ap;
+    cg->hx = cg->hi ? (double*)(dev + w.hx) : nullptr;
+    cg->host = host;
+}
+
+}  // namespace
 
 extern "C" {
 
-btoep_status btoep_cg_end(btoep_cg cg) {
-    if (!cg) return BTOEP_ERR_INVALID_ARG;
-    DeviceGuard g(cg->op->device);
-    (void)hipDeviceSynchronize();
-    for (void* q : {cg->r, cg->p, cg->Ap, (void*)cg->sc, (void*)cg->tmp})
-        if (q) (void)hipFree(q);
-    if (cg->host) (void)hipHostFree(cg->host);
-    if (cg->ev) (void)hipEventDestroy(cg->ev);
-    delete cg;
+btoep_status btoep_cg_workspace_size(btoep_op op_lo, btoep_op op_hi, int64_t k, size_t* bytes) {
+    if (!op_lo || !bytes || k < 0 || !cg_pair_ok(op_lo, op_hi)) return BTOEP_ERR_INVALID_ARG;
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(k, kMaxBatch));
+    *bytes = cg_layout(op_lo, op_hi, nb).total;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_state_size(btoep_op op_lo, btoep_op op_hi, int64_t k, size_t* dev_bytes,
+                                 size_t* host_bytes) {
+    if (!op_lo || !dev_bytes || !host_bytes || k < 1 || k > kMaxBatch || !cg_pair_ok(op_lo, op_hi))
+        return BTOEP_ERR_INVALID_ARG;
+    const CgStateLayout w = cg_state_layout(op_lo, op_hi, k);
+    *dev_bytes = w.total;
+    *host_bytes = w.host;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_begin(btoep_op op_lo, btoep_op op_hi, int64_t k, const void* b, void* x, double rtol,
+                            double inner_rtol, void* dev_mem, size_t dev_bytes, void* host_mem, size_t host_bytes,
+                            void* stream, btoep_cg* out) {
+    if (!out) return BTOEP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!op_lo || !b || !x || k < 1 || k > kMaxBatch || !(rtol > 0.0) || !dev_mem || !host_mem)
+        return BTOEP_ERR_INVALID_ARG;
+    if (!cg_pair_ok(op_lo, op_hi) || (op_hi && !(inner_rtol > 0.0 && inner_rtol < 1.0)))
+        return BTOEP_ERR_INVALID_ARG;
+    if ((uintptr_t)dev_mem % 256 != 0 || (uintptr_t)host_mem % alignof(double) != 0) return BTOEP_ERR_INVALID_ARG;
+    const CgStateLayout w = cg_state_layout(op_lo, op_hi, k);
+    if (dev_bytes < w.total || host_bytes < w.host) return BTOEP_ERR_WORKSPACE_TOO_SMALL;
+    btoep_cg cg = new (std::nothrow) btoep_cg_s();
+    if (!cg) return BTOEP_ERR_OUT_OF_MEMORY;
+    cg->op = op_lo;
+    cg->hi = op_hi;
+    cg->k = k;
+    cg->n = op_lo->Nt * op_lo->Nm;
+    cg->b = b;
+    cg->x = x;
+    cg->rtol2 = rtol * rtol;
+    cg->inner_rtol2 = inner_rtol * inner_rtol;
+    cg_bind(cg, w, (char*)dev_mem, (double*)host_mem);
+    DeviceGuard g(op_lo->device);
+    hipError_t e = hipEventCreateWithFlags(&cg->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = cg_init(cg, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        const btoep_status s = cg_err(op_lo, "cg_begin", e);
+        cg_free(cg);
+        return s;
+    }
+    *out = cg;
     return BTOEP_OK;
 }
 
@@ -1413,45 +1555,44 @@ btoep_status btoep_cg_start(btoep_op op, int64_t k, double noise_prec, double pr
                             double rtol, void* stream, btoep_cg* out) {
     (void)noise_prec;
     (void)prior_prec;
-    if (!op || !out || !b || !x || k < 1 || k > kMaxBatch || !(rtol > 0.0)) return BTOEP_ERR_INVALID_ARG;
+    if (!out) return BTOEP_ERR_INVALID_ARG;
     *out = nullptr;
+    if (!op || !b || !x || k < 1 || k > kMaxBatch || !(rtol > 0.0)) return BTOEP_ERR_INVALID_ARG;
     btoep_cg cg = new (std::nothrow) btoep_cg_s();
     if (!cg) return BTOEP_ERR_OUT_OF_MEMORY;
     cg->op = op;
     cg->k = k;
     cg->n = op->Nt * op->Nm;
+    cg->b = b;
     cg->x = x;
+    cg->rtol2 = rtol * rtol;
+    const CgStateLayout w = cg_state_layout(op, nullptr, k);
     DeviceGuard g(op->device);
-    hipStream_t st = (hipStream_t)stream;
-    const size_t vb = (size_t)k * cg->n * vbytes(op);
-    const Real rv = op->vreal;
-    hipError_t e = hipMalloc(&cg->r, vb);
-    if (e == hipSuccess) e = hipMalloc(&cg->p, vb);
-    if (e == hipSuccess) e = hipMalloc(&cg->Ap, vb);
-    if (e == hipSuccess) e = hipMalloc((void**)&cg->sc, (size_t)k * kScal * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&cg->tmp, dot_tmp_doubles((int)k) * sizeof(double));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&cg->host, (size_t)k * kScal * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&cg->ev, hipEventDisableTiming);
-    const int nb = (int)k;
-    const int64_t n = cg->n;
+    double* host = nullptr;
+    hipError_t e = hipMalloc(&cg->owned_dev, w.total);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&host, w.host, hipHostMallocDefault);
     if (e == hipSuccess) {
-        std::vector<double> zeros((size_t)k * kScal, 0.0);
-        e = hipMemcpyAsync(cg->sc, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        cg->owned_host = true;
+        cg_bind(cg, w, (char*)cg->owned_dev, host);
+        e = hipEventCreateWithFlags(&cg->ev, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = launch_axpbz(rv, x, 0.0, rv, b, 0.0, rv, nullptr, n, nb, n, st);      // x = 0
-    if (e == hipSuccess) e = launch_axpbz(rv, cg->r, 1.0, rv, b, 0.0, rv, nullptr, n, nb, n, st);  // r = b
-    if (e == hipSuccess) e = launch_axpbz(rv, cg->p, 1.0, rv, b, 0.0, rv, nullptr, n, nb, n, st);  // p = b
-    for (int slot : {kScRR, kScBB, kScRH})
-        if (e == hipSuccess) e = launch_dot(rv, b, b, n, nb, n, cg->sc, slot, 0, cg->tmp, st);
-    // stop on ||r||^2 <= rtol^2 ||b||^2; outer test 0 keeps every nonzero right-hand side active
-    if (e == hipSuccess) e = launch_cg_init_scalars(cg->sc, nb, rtol * rtol, 0.0, st);
+    if (e == hipSuccess) e = cg_init(cg, (hipStream_t)stream);
     if (e != hipSuccess) {
-        set_err(op, "cg_start", e);
-        btoep_cg_end(cg);
-        return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+        const btoep_status s = cg_err(op, "cg_start", e);
+        if (host && !cg->owned_host) (void)hipHostFree(host);
+        (void)hipDeviceSynchronize();
+        cg_free(cg);
+        return s;
     }
     *out = cg;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_end(btoep_cg cg) {
+    if (!cg) return BTOEP_ERR_INVALID_ARG;
+    DeviceGuard g(cg->op->device);
+    if (cg->owned_dev) (void)hipDeviceSynchronize();  // the state's own memory is freed below
+    cg_free(cg);
     return BTOEP_OK;
 }
 
@@ -1462,18 +1603,41 @@ btoep_status btoep_cg_vectors(btoep_cg cg, void** p, void** Ap) {
     return BTOEP_OK;
 }
 
+btoep_status btoep_cg_residual_vectors(btoep_cg cg, void** x, void** Hx) {
+    if (!cg || !x || !Hx || !cg->hi) return BTOEP_ERR_INVALID_ARG;
+    *x = cg->x;
+    *Hx = cg->hx;
+    return BTOEP_OK;
+}
+
 btoep_status btoep_cg_update(btoep_cg cg, void* stream) {
     if (!cg) return BTOEP_ERR_INVALID_ARG;
     btoep_op op = cg->op;
     DeviceGuard g(op->device);
     hipStream_t st = (hipStream_t)stream;
-    const Real rv = op->vreal;
+    const Real rv = op->vreal, rx = cg->hi ? Real::F64 : rv;
     const int nb = (int)cg->k;
     const int64_t n = cg->n;
     BT_HIP(op, launch_dot(rv, cg->p, cg->Ap, n, nb, n, cg->sc, kScPAP, kScPAP, cg->tmp, st));
-    BT_HIP(op, launch_cg_xr(rv, rv, cg->x, cg->r, cg->p, cg->Ap, n, nb, n, cg->sc, st));
+    BT_HIP(op, launch_cg_xr(rv, rx, cg->x, cg->r, cg->p, cg->Ap, n, nb, n, cg->sc, st));
     BT_HIP(op, launch_dot(rv, cg->r, cg->r, n, nb, n, cg->sc, kScRRN, kScRRN, cg->tmp, st));
     BT_HIP(op, launch_cg_p(rv, cg->p, cg->r, n, nb, n, cg->sc, st));
+    ++cg->updates;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_refine(btoep_cg cg, void* stream) {
+    if (!cg || !cg->hi) return BTOEP_ERR_INVALID_ARG;
+    btoep_op op = cg->op;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = (int)cg->k;
+    const int64_t n = cg->n;
+    // true residual in FP64: hx = b - H_hi x, RH = <hx, hx>
+    BT_HIP(op, launch_axpbz(Real::F64, cg->hx, -1.0, Real::F64, cg->hx, 1.0, Real::F64, cg->b, n, nb, n, st));
+    BT_HIP(op, launch_dot(Real::F64, cg->hx, cg->hx, n, nb, n, cg->sc, kScRH, 0, cg->tmp, st));
+    BT_HIP(op, cg_restart(cg, cg->hx, Real::F64, cg->rtol2, 0.25 * cg->rtol2, st));
+    ++cg->outer;
     return BTOEP_OK;
 }
 
@@ -1485,20 +1649,38 @@ btoep_status btoep_cg_poll(btoep_cg cg, void* stream) {
     BT_HIP(op, hipMemcpyAsync(cg->host, cg->sc, (size_t)cg->k * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
     BT_HIP(op, hipEventRecord(cg->ev, st));
     cg->polled = true;
+    cg->seen_outer = cg->outer;
+    cg->seen_updates = cg->updates;
     return BTOEP_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// 1 when the last poll has landed, 0 while it is in flight or none was made, <0 on error.
+int cg_landed(btoep_cg cg) {
+    if (!cg->polled) return 0;
+    DeviceGuard g(cg->op->device);
+    const hipError_t q = hipEventQuery(cg->ev);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) {
+        set_err(cg->op, "cg poll", q);
+        return -1;
+    }
+    return 1;
+}
+
+}  // namespace
+
+extern "C" {
 
 btoep_status btoep_cg_status(btoep_cg cg, int* ready, int* active, int* iters, double* rel_res) {
     if (!cg || !ready) return BTOEP_ERR_INVALID_ARG;
     *ready = 0;
-    if (!cg->polled) return BTOEP_OK;
-    DeviceGuard g(cg->op->device);
-    const hipError_t q = hipEventQuery(cg->ev);
-    if (q == hipErrorNotReady) return BTOEP_OK;
-    if (q != hipSuccess) {
-        set_err(cg->op, "cg_status", q);
-        return BTOEP_ERR_HIP;
-    }
+    const int l = cg_landed(cg);
+    if (l < 0) return BTOEP_ERR_HIP;
+    if (l == 0) return BTOEP_OK;
     *ready = 1;
     int act = 0, it = 0;
     for (int64_t i = 0; i < cg->k; ++i) {
@@ -1509,6 +1691,25 @@ btoep_status btoep_cg_status(btoep_cg cg, int* ready, int* active, int* iters, d
     }
     if (active) *active = act;
     if (iters) *iters = it;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_cg_report(btoep_cg cg, int* ready, btoep_cg_result* results) {
+    if (!cg || !ready || !results) return BTOEP_ERR_INVALID_ARG;
+    *ready = 0;
+    const int l = cg_landed(cg);
+    if (l < 0) return BTOEP_ERR_HIP;
+    if (l == 0) return BTOEP_OK;
+    *ready = 1;
+    for (int64_t i = 0; i < cg->k; ++i) {
+        const double* h = cg->host + i * kScal;
+        const double bb = h[kScBB], res2 = cg->hi ? h[kScRH] : h[kScRR];
+        results[i].inner_iters = (int)h[kScIT];
+        results[i].outer_iters = cg->seen_outer;
+        results[i].matvecs = cg->seen_updates + cg->seen_outer;
+        results[i].converged = res2 <= cg->rtol2 * bb ? 1 : 0;
+        results[i].rel_residual = bb > 0 ? std::sqrt(res2 / bb) : std::sqrt(res2);
+    }
     return BTOEP_OK;
 }
 

@@ -26,8 +26,12 @@ hipError_t launch_cg_p(Real rv, void* p, const void* r, int64_t n, int nb, int64
 // y = a x + c z (z may be null), elementwise with type conversion.
 hipError_t launch_axpbz(Real ry, void* y, double a, Real rx, const void* x, double c, Real rz, const void* z,
                         int64_t n, int nb, int64_t stride, hipStream_t s);
-// Start of an inner CG solve: TH = inner_rtol2 * RR, AL = BE = 0, and ACT = 1 only where
-// RR > TH and the true residual has not yet met the outer test RH > outer_rtol2 * BB.
-hipError_t launch_cg_init_scalars(double* sc, int nb, double inner_rtol2, double outer_rtol2, hipStream_t s);
+// Start of an inner CG solve: TH = max(inner_rtol2 * RR, floor2 * BB), AL = BE = 0, and
+// ACT = 1 only where RR > TH and the true residual has not yet met the outer test
+// RH > outer_rtol2 * BB.
+hipError_t launch_cg_init_scalars(double* sc, int nb, double inner_rtol2, double outer_rtol2, double floor2,
+                                  hipStream_t s);
+// y[i] = 0 for i < n (a kernel, so that it may be captured into a graph).
+hipError_t launch_zero(Real r, void* y, int64_t n, hipStream_t s);
 
 }  // namespace btoep

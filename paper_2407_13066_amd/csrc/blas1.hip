@@ -168,19 +168,36 @@ hipError_t launch_axpbz(Real ry, void* y, double a, Real rx, const void* x, doub
     return hipGetLastError();
 }
 
-__global__ void k_cg_init_scalars(double* sc, int nb, double inner_rtol2, double outer_rtol2) {
+__global__ void k_cg_init_scalars(double* sc, int nb, double inner_rtol2, double outer_rtol2, double floor2) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     double* q = sc + (int64_t)b * kScal;
-    q[kScTH] = inner_rtol2 * q[kScRR];
+    q[kScTH] = fmax(inner_rtol2 * q[kScRR], floor2 * q[kScBB]);
     const bool outer = q[kScRH] > outer_rtol2 * q[kScBB];
     q[kScACT] = (outer && q[kScRR] > q[kScTH] && q[kScRR] > 0.0) ? 1.0 : 0.0;
     q[kScAL] = 0.0;
     q[kScBE] = 0.0;
 }
 
-hipError_t launch_cg_init_scalars(double* sc, int nb, double inner_rtol2, double outer_rtol2, hipStream_t s) {
-    k_cg_init_scalars<<<(nb + 63) / 64, 64, 0, s>>>(sc, nb, inner_rtol2, outer_rtol2);
+hipError_t launch_cg_init_scalars(double* sc, int nb, double inner_rtol2, double outer_rtol2, double floor2,
+                                  hipStream_t s) {
+    k_cg_init_scalars<<<(nb + 63) / 64, 64, 0, s>>>(sc, nb, inner_rtol2, outer_rtol2, floor2);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecThreads)
+        y[i] = T(0);
+}
+
+hipError_t launch_zero(Real r, void* y, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 g = vgrid(n, 1);
+    if (r == Real::F64)
+        k_zero<double><<<g, kVecThreads, 0, s>>>((double*)y, n);
+    else
+        k_zero<float><<<g, kVecThreads, 0, s>>>((float*)y, n);
     return hipGetLastError();
 }
 

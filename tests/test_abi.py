@@ -125,3 +125,22 @@ def test_malformed_operator_files_rejected_before_device_work(lib, tmp_path, cas
 def test_alt_form_arguments_rejected(lib):
     assert lib.btoep_alt_prepare(None, 1, None) == 1
     assert lib.btoep_alt_apply(None, 0, 1, None, None, None) == 1
+
+
+def test_stepwise_cg_arguments_rejected(lib):
+    """The caller-memory CG entry points check their arguments on the host."""
+    dev, host = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.btoep_cg_state_size(None, None, 1, ctypes.byref(dev), ctypes.byref(host)) == 1
+    assert lib.btoep_cg_workspace_size(None, None, 1, ctypes.byref(dev)) == 1
+    h = ctypes.c_void_p()
+    assert lib.btoep_cg_begin(None, None, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), 1e-6, 1e-3,
+                              ctypes.c_void_p(256), 1 << 20, ctypes.c_void_p(8), 1 << 10, None,
+                              ctypes.byref(h)) == 1
+    assert lib.btoep_cg_begin(None, None, 1, None, None, 1e-6, 1e-3, None, 0, None, 0, None, None) == 1
+    for f in (lib.btoep_cg_refine, lib.btoep_cg_update, lib.btoep_cg_poll):
+        assert f(None, None) == 1
+    x, hx = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lib.btoep_cg_residual_vectors(None, ctypes.byref(x), ctypes.byref(hx)) == 1
+    ready = ctypes.c_int()
+    assert lib.btoep_cg_report(None, ctypes.byref(ready), None) == 1
+    assert lib.btoep_cg_end(None) == 1

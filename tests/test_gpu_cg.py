@@ -11,7 +11,7 @@ import torch
 import oracle
 import synth
 from tests import pins
-from tests.gpu_helpers import make, to_dev
+from tests.gpu_helpers import make, stepwise_cg, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -157,3 +157,54 @@ def test_stepwise_cg_with_a_caller_applied_prior(bt):
     assert ready and active == 0, (iters, rel)
     assert oracle.rel_l2(x[0].cpu().numpy(), x_ref) <= 1e-9
     bt.btoep_cg_end(cg)
+
+
+@pytest.mark.parametrize("lo_storage", ["f32", "f64"])
+def test_stepwise_refined_cg_on_caller_memory(bt, lo_storage):
+    """btoep_cg_begin / update / refine / report on caller memory: the FP32 (or FP64) inner
+    iteration with FP64 true residuals meets 1e-8 on the oracle's H with the inverse-problem
+    scalars (sigma = 1e-2, alpha = 1e-3), the report's residual is the true one, and the
+    solution agrees in data space with btoep_cg_solve's."""
+    rng = np.random.default_rng(25)
+    Nt, Nd, Nm, k = 48, 6, 700, 3
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / (Nt / 7))[:, None, None]
+    noise_prec, alpha, rtol = 1e4, 1e-3, 1e-8
+    b = noise_prec * oracle.apply_FT(blocks, rng.standard_normal((k, Nt, Nd)))
+    hi = make(bt, blocks, "f64")
+    lo = make(bt, blocks, lo_storage) if lo_storage != "f64" else hi
+    print("case stepwise refined", lo_storage, flush=True)
+    x, rep, steps = stepwise_cg(bt, lo, hi, to_dev(b, torch.float64), rtol, noise_prec, alpha, inner_rtol=1e-4,
+                                max_iter=2000)
+    x = x.cpu().numpy()
+    st, res, xs = solve(bt, lo, hi, b, noise_prec, alpha, rtol=rtol, inner_rtol=1e-4)
+    assert st == 0
+    for r in range(k):
+        assert rep[r]["converged"] and rep[r]["rel_residual"] <= rtol and rep[r]["outer_iters"] >= 1, rep
+        true = np.linalg.norm(b[r] - oracle.apply_H(blocks, x[r], noise_prec, alpha)) / np.linalg.norm(b[r])
+        assert true <= 1.01 * rtol
+        assert abs(true - rep[r]["rel_residual"]) <= 0.05 * rtol
+        Fd = oracle.apply_F(blocks, x[r] - xs[r])
+        assert np.linalg.norm(Fd) <= 1e-6 * np.linalg.norm(oracle.apply_F(blocks, xs[r]))
+
+
+def test_stepwise_state_arguments_checked(bt):
+    blocks = np.ones((8, 2, 3))
+    lo = make(bt, blocks, "f32")
+    hi = make(bt, blocks, "f64")
+    other = make(bt, np.ones((8, 2, 4)), "f64")
+    dev, host = bt.btoep_cg_state_size(lo, hi, 2)
+    dev_lo, _ = bt.btoep_cg_state_size(lo, None, 2)
+    assert dev > dev_lo > 0 and host == 2 * 12 * 8
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_cg_state_size(lo, other, 2)           # shapes differ
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_cg_state_size(lo, lo, 2)              # refinement operator must be FP64
+    b = torch.zeros((2, 8, 3), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    dm = torch.empty(dev - 256, dtype=torch.uint8, device="cuda")
+    hm = torch.empty(host, dtype=torch.uint8, pin_memory=True)
+    with pytest.raises(bt.BtoepError, match="workspace"):
+        bt.btoep_cg_begin(lo, hi, b, x, 1e-8, 1e-4, dm, hm)
+    with pytest.raises(ValueError):
+        bt.btoep_cg_begin(lo, hi, b.float(), x.float(), 1e-8, 1e-4, dm, hm)   # refined: FP64 vectors
+    assert bt.btoep_cg_workspace_size(lo, hi, 2) > bt.btoep_cg_workspace_size(lo, None, 2)

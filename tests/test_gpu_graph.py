@@ -103,6 +103,25 @@ def test_graph_replayed_back_to_back_on_one_stream(bt):
             assert torch.equal(got[r], want[r])
 
 
+def test_graph_replay_without_vectors_before_any_is_rejected(bt):
+    """A graph launched with no vectors before any launch gave some returns INVALID_ARG and
+    launches nothing; after one launch with vectors, a vector-less launch replays on them."""
+    blocks = synth.blocks(8, 2, 16, tau=4.0, seed=78)
+    op = make(bt, blocks, "f32")
+    g = bt.ApplyGraph(op, "F", 1)
+    with pytest.raises(bt.BtoepError) as e:
+        g.launch()
+    assert e.value.status == 1
+    m = torch.randn((1, 8, 16), device="cuda")
+    d = torch.zeros((1, 8, 2), device="cuda")
+    g.launch([m.data_ptr()], [d.data_ptr()])
+    d.zero_()
+    g.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(d, bt.btoep_apply_F(op, m))
+    g.destroy()
+
+
 def test_graph_rejects_small_workspace(bt):
     blocks = synth.blocks(8, 2, 16, tau=4.0, seed=79)
     op = make(bt, blocks, "f32")

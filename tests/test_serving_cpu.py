@@ -20,11 +20,20 @@ class FakeClock:
 
 
 class OracleExecutor:
-    """Executes each batch with the oracle; a batch 'completes' `delay` seconds after launch."""
+    """Executes each batch with the oracle; a batch 'completes' `delay` seconds after launch.
 
-    def __init__(self, ops, clock, delay=5e-3, vbytes=4):
-        self.ops, self.clock, self.delay, self.vb = ops, clock, delay, vbytes
+    CG follows the library's stepwise protocol.  With ``refine`` the inner iterations apply H
+    built from the blocks rounded to float32 (a stand-in for the stored low-precision operator)
+    and every refinement step forms the true residual with the exact FP64 operator, so that
+    refinement has something to correct."""
+
+    def __init__(self, ops, clock, delay=5e-3, vbytes=4, refine=False):
+        self.ops, self.clock, self.delay, self.vb, self.refine = ops, clock, delay, vbytes, refine
+        self.ops_lo = {n: b.astype(np.float32).astype(np.float64) for n, b in ops.items()}
         self.batches = []
+
+    def refined(self, req):
+        return self.refine and req.kind == "CG"
 
     def request_bytes(self, req):
         Nt, Nd, Nm = self.ops[req.op].shape
@@ -32,29 +41,54 @@ class OracleExecutor:
         n_out = req.k * Nt * (Nd if req.kind == "F" else Nm)
         return (n_in + n_out + (3 * req.k * Nt * Nm if req.kind == "CG" else 0)) * self.vb
 
+    @staticmethod
+    def _dot(a, b):
+        return (a * b).sum(axis=(1, 2))
+
+    def _restart(self, req, res, outer_test):
+        st = req._state
+        st["r"] = res.copy()
+        st["p"] = res.copy()
+        st["rr"] = self._dot(res, res)
+        floor = 0.25 * req.rtol ** 2 * st["bb"] if self.refined(req) else 0.0
+        inner2 = req.inner_rtol ** 2 if self.refined(req) else req.rtol ** 2
+        st["th"] = np.maximum(inner2 * st["rr"], floor)
+        st["act"] = (st["rh"] > outer_test * st["bb"]) & (st["rr"] > st["th"])
+
     def begin(self, req):
         if req.kind == "CG":
             b = np.asarray(req.x, dtype=np.float64)
-            req._state = {"x": np.zeros_like(b), "r": b.copy(), "p": b.copy(), "rr": (b * b).sum(axis=(1, 2)),
-                          "bb": (b * b).sum(axis=(1, 2)), "it": np.zeros(req.k, int), "snap": None}
+            bb = self._dot(b, b)
+            req._state = {"b": b, "x": np.zeros_like(b), "bb": bb, "rh": bb.copy(), "it": np.zeros(req.k, int),
+                          "outer": 0, "snap": None}
+            self._restart(req, b, req.rtol ** 2 if self.refined(req) else 0.0)
 
-    def launch(self, op, pipe, noise, prior, batch, stream):
+    def launch(self, op, pipe, noise, prior, batch, stream, hi=False):
         blocks = self.ops[op]
-        self.batches.append((op, pipe, sum(r.k for r in batch), [r.rid for r in batch]))
+        self.batches.append((op, pipe + ("64" if hi else ""), sum(r.k for r in batch), [r.rid for r in batch]))
         for req in batch:
             if req.kind == "CG":
                 st = req._state
-                act = st["rr"] > req.rtol ** 2 * st["bb"]
-                Ap = oracle.apply_H(blocks, st["p"], noise, prior)
-                pAp = (st["p"] * Ap).sum(axis=(1, 2))
-                al = np.where(act, st["rr"] / pAp, 0.0)
-                st["x"] += al[:, None, None] * st["p"]
-                st["r"] -= al[:, None, None] * Ap
-                rrn = (st["r"] * st["r"]).sum(axis=(1, 2))
-                be = np.where(act, rrn / st["rr"], 0.0)
-                st["p"] = np.where(act[:, None, None], st["r"] + be[:, None, None] * st["p"], st["p"])
-                st["it"] += act
-                st["rr"] = np.where(act, rrn, st["rr"])
+                if hi:
+                    res = st["b"] - oracle.apply_H(blocks, st["x"], noise, prior)
+                    st["rh"] = self._dot(res, res)
+                    st["outer"] += 1
+                    self._restart(req, res, req.rtol ** 2)
+                else:
+                    lo = self.ops_lo[op] if self.refined(req) else blocks
+                    act = st["act"]
+                    Ap = oracle.apply_H(lo, st["p"], noise, prior)
+                    al = np.where(act, st["rr"] / self._dot(st["p"], Ap), 0.0)
+                    st["x"] += al[:, None, None] * st["p"]
+                    st["r"] -= al[:, None, None] * Ap
+                    rrn = self._dot(st["r"], st["r"])
+                    be = np.where(act, rrn / st["rr"], 0.0)
+                    st["p"] = np.where(act[:, None, None], st["r"] + be[:, None, None] * st["p"], st["p"])
+                    st["it"] += act
+                    st["rr"] = np.where(act, rrn, st["rr"])
+                    st["act"] = act & (rrn > st["th"])
+                if req._poll_due:
+                    self.cg_poll(req, stream)
             elif pipe == "F":
                 req.out = oracle.apply_F(blocks, req.x)
             elif pipe == "FT":
@@ -68,11 +102,19 @@ class OracleExecutor:
 
     def cg_poll(self, req, stream):
         st = req._state
-        st["snap"] = (self.clock.t + self.delay, int((st["rr"] > req.rtol ** 2 * st["bb"]).sum()), int(st["it"].max()))
+        res2 = st["rh"] if self.refined(req) else st["rr"]
+        results = [dict(inner_iters=int(st["it"][r]), outer_iters=st["outer"], matvecs=0,
+                        converged=bool(res2[r] <= req.rtol ** 2 * st["bb"][r]),
+                        rel_residual=float(np.sqrt(res2[r] / st["bb"][r]))) for r in range(req.k)]
+        st["snap"] = (self.clock.t + self.delay, int(st["act"].sum()), int(st["it"].max()), results)
 
     def cg_status(self, req):
-        t, active, iters = req._state["snap"]
+        t, active, iters, _ = req._state["snap"]
         return (self.clock.t >= t), active, iters
+
+    def cg_report(self, req):
+        t, _, _, results = req._state["snap"]
+        return (self.clock.t >= t), results
 
     def finish(self, req):
         if req.kind == "CG":
@@ -123,6 +165,31 @@ def test_results_match_solo_oracle_and_everything_completes():
             continue
         assert oracle.rel_l2(req.out, want) == 0.0
         assert req.latency is not None and req.latency > 0
+
+
+def test_refined_cg_meets_the_true_residual():
+    """With a float32-rounded inner operator, CG converges only through refinement: every
+    solve ends with a true (exact-operator) residual at or below rtol, after at least one
+    refinement step, and the refinement applies show up as their own pipeline."""
+    rng = np.random.default_rng(5)
+    ops = make_ops(rng)
+    clock = FakeClock()
+    ex = OracleExecutor(ops, clock, refine=True)
+    srv = Server(ex, hbm_budget=1 << 30, max_batch=8, n_streams=2, clock=clock)
+    arrivals = make_requests(rng, ops, 12, kinds=("CG", "H"))
+    for _, req in arrivals:
+        req.rtol, req.inner_rtol = 1e-12, 1e-3
+    srv.run(arrivals, t0=0.0)
+    assert srv.idle() and srv.used == 0
+    for _, req in arrivals:
+        if req.kind != "CG":
+            continue
+        assert req.converged and req.outer >= 1
+        for r in range(req.k):
+            res = req.x[r] - oracle.apply_H(ops[req.op], req.out[r], 2.0, 1.0)
+            assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(req.x[r]) * (1 + 1e-9)
+            assert req.rel_residual[r] <= 1e-12
+    assert srv.rhs_applies["H64"] > 0 and any(p == "H64" for (_, p, _, _) in ex.batches)
 
 
 def test_requests_are_batched_across_arrivals():
