@@ -193,6 +193,23 @@ btoep_status btoep_apply_H(btoep_op op, int64_t k, double noise_prec, double pri
                            void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The three applies without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * same launches and chunking as btoep_apply_F / _FT / _H (which = BTOEP_APPLY_F, _FT or _H;
+ * noise_prec / prior_prec used by _H only; in / out laid out as for those calls), so the
+ * results are bitwise the same, but the workspace is a static device array of
+ * BTOEP_STATIC_SCRATCH_BYTES that the library holds on each device it runs on until the
+ * process ends.  Calls on one device share that array: calls that overlap on one device
+ * (other streams, other threads) race and must not be issued.  Nothing in it needs to start
+ * at zero.  Errors: INVALID_ARG (as btoep_apply_*), WORKSPACE_TOO_SMALL when
+ * btoep_workspace_size(op, which, min(k, BTOEP_MAX_BATCH)) exceeds BTOEP_STATIC_SCRATCH_BYTES
+ * (nothing launched; btoep_last_error names both sizes), HIP.
+ */
+#define BTOEP_STATIC_SCRATCH_BYTES (128u << 20)
+btoep_status btoep_apply_static(btoep_op op, btoep_which which, int64_t k, double noise_prec, double prior_prec,
+                                const void* in, void* out, void* stream);
+
+/*
  * Pointer-array form of the three applies for right-hand sides that do not sit in one
  * array (e.g. requests batched by a server): in[r] / out[r] (HOST arrays of k <=
  * BTOEP_MAX_BATCH device pointers) each point at one [Nt][Nm] or [Nt][Nd] vector.

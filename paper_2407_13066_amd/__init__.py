@@ -18,11 +18,13 @@ LIB_PATH = os.path.join(HERE, "libbtoep.so")
 
 BTOEP_OK = 0
 BTOEP_ERR_NOT_CONVERGED = 5
+BTOEP_ERR_WORKSPACE_TOO_SMALL = 6
 BTOEP_ERR_IO = 7
 ORDER = {"column": 0, "last_row": 1}
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 WHICH = {"F": 0, "FT": 1, "H": 2, "CG": 3}
 MAX_BATCH = 64
+STATIC_SCRATCH_BYTES = 128 << 20   # BTOEP_STATIC_SCRATCH_BYTES
 
 _lib = None
 
@@ -89,6 +91,7 @@ def load_library(path=LIB_PATH):
         "btoep_apply_H": ([vp, i64, dbl, dbl, vp, vp, vp, sz, vp], st),
         "btoep_apply_batched": ([vp, ctypes.c_int, i64, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, dbl, vp, sz,
                                  vp], st),
+        "btoep_apply_static": ([vp, ctypes.c_int, i64, dbl, dbl, vp, vp, vp], st),
         "btoep_graph_create": ([vp, ctypes.c_int, i64, dbl, dbl, vp, sz, ctypes.POINTER(vp)], st),
         "btoep_graph_launch": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], st),
         "btoep_graph_destroy": ([vp], st),
@@ -386,6 +389,21 @@ def btoep_apply_H(op, m, noise_prec=1.0, prior_prec=1.0, out=None, ws=None, stre
                                         wp, wn, _stream(stream)),
            "btoep_apply_H", op.handle)
     return o3[0] if squeeze else out
+
+
+def btoep_apply_static(op, which, x, out, noise_prec=1.0, prior_prec=1.0, stream=None):
+    """F, F^T or H (``which``) of x into ``out`` with the library's static device scratch as the
+    workspace (btoep_apply_static: no allocation; calls on one device must not overlap)."""
+    tin, tout = _io_tails(op, which)
+    x3 = _vec(op, x, tin, "x")
+    o3 = _vec(op, out, tout, "out")
+    if o3.shape[0] != x3.shape[0]:
+        raise ValueError("x and out hold different numbers of right-hand sides")
+    _check(load_library().btoep_apply_static(op.handle, WHICH[which], x3.shape[0], float(noise_prec),
+                                             float(prior_prec), ctypes.c_void_p(x3.data_ptr()),
+                                             ctypes.c_void_p(o3.data_ptr()), _stream(stream)),
+           "btoep_apply_static", op.handle)
+    return out
 
 
 def btoep_apply_batched(op, which, ins, outs, noise_prec=1.0, prior_prec=1.0, ws=None, stream=None):

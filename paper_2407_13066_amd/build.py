@@ -29,10 +29,29 @@ def hipcc():
 
 
 def build(verbose=False):
-    """Compile every HIP source into paper_2407_13066_amd/libbtoep.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile every HIP source into paper_2407_13066_amd/libbtoep.so (always recompiles).
+
+    Each source becomes an object of its own (compiled in parallel; no device code crosses
+    translation units), then hipcc links the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    obj_dir = os.path.join(ROOT, "_build", "btoep")
+    os.makedirs(obj_dir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
+        cmd = [hipcc()] + flags + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + srcs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -920,6 +920,59 @@ btoep_status btoep_apply_H(btoep_op op, int64_t k, double noise_prec, double pri
     return apply_contig(op, BTOEP_APPLY_H, k, m, Hm, noise_prec, prior_prec, ws, ws_bytes, stream);
 }
 
+}  // extern "C"
+
+// ---- applies without allocation --------------------------------------------------------
+// The workspace of btoep_apply_static: one array per device, alive until the process ends.
+// Host code never passes `scratch` itself to a kernel: its device address, per device, comes
+// from hipGetSymbolAddress on the first call on that device.
+static __device__ __align__(256) char scratch[BTOEP_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of this device's scratch array (looked up once per device, with it current).
+btoep_status scratch_ptr(btoep_op op, void** out) {
+    if (op->device < 0 || op->device >= kMaxDevices) return BTOEP_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[op->device]) {
+        DeviceGuard g(op->device);
+        void* p = nullptr;
+        BT_HIP(op, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[op->device] = p;
+    }
+    *out = g_scratch_ptr[op->device];
+    return BTOEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+btoep_status btoep_apply_static(btoep_op op, btoep_which which, int64_t k, double noise_prec, double prior_prec,
+                                const void* in, void* out, void* stream) {
+    if (!op || k < 0) return BTOEP_ERR_INVALID_ARG;
+    if (which != BTOEP_APPLY_F && which != BTOEP_APPLY_FT && which != BTOEP_APPLY_H) return BTOEP_ERR_INVALID_ARG;
+    if (k == 0) return BTOEP_OK;
+    if (!in || !out || (which == BTOEP_APPLY_H && in == out)) return BTOEP_ERR_INVALID_ARG;
+    const size_t need = apply_layout(op, which, std::min<int64_t>(k, kMaxBatch)).total;
+    if (need > (size_t)BTOEP_STATIC_SCRATCH_BYTES) {
+        snprintf(op->err, sizeof(op->err),
+                 "btoep_apply_static: this apply needs %zu bytes of workspace, the static scratch holds %zu "
+                 "(use fewer right-hand sides or pass a workspace to btoep_apply_*)",
+                 need, (size_t)BTOEP_STATIC_SCRATCH_BYTES);
+        return BTOEP_ERR_WORKSPACE_TOO_SMALL;
+    }
+    void* ws = nullptr;
+    const btoep_status s = scratch_ptr(op, &ws);
+    if (s != BTOEP_OK) return s;
+    return apply_contig(op, which, k, in, out, noise_prec, prior_prec, ws, (size_t)BTOEP_STATIC_SCRATCH_BYTES,
+                        stream);
+}
+
 btoep_status btoep_apply_batched(btoep_op op, btoep_which which, int64_t k, const void* const* in, void* const* out,
                                  double noise_prec, double prior_prec, void* ws, size_t ws_bytes, void* stream) {
     if (!op || k < 0 || k > kMaxBatch) return BTOEP_ERR_INVALID_ARG;
