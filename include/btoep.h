@@ -399,6 +399,19 @@ btoep_status btoep_cg_status(btoep_cg cg, int* ready, int* active, int* iters, d
 btoep_status btoep_cg_report(btoep_cg cg, int* ready, btoep_cg_result* results);
 btoep_status btoep_cg_end(btoep_cg cg);
 
+/*
+ * Measurement support: streams one device array of `bytes` (>= 1 MiB) through a kernel of
+ * non-temporal 16-byte loads, `reps` times for each of six launch shapes (4 or 8 loads in
+ * flight per lane, 4, 8 or 16 workgroups per CU) on `stream` (the current device), and returns,
+ * for the shape with the lowest mean, the best time and the best and mean read rates
+ * (GB/s = 1e9 bytes/s).  This is the rate the
+ * memory system gives one streaming read, against which the operator-streaming product
+ * kernels (section 4.1 reads its kernels against peak bandwidth) are compared.  Allocates
+ * and frees the array (synchronises the device).  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+btoep_status btoep_read_bandwidth(size_t bytes, int reps, void* stream, double* best_ms, double* best_gbs,
+                                  double* mean_gbs);
+
 /* Static text for a status code. */
 const char* btoep_status_string(btoep_status s);
 

@@ -115,6 +115,8 @@ def load_library(path=LIB_PATH):
         "btoep_cg_refine": ([vp, vp], st),
         "btoep_cg_report": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(CgResult)], st),
         "btoep_cg_workspace_size": ([vp, vp, i64, ctypes.POINTER(sz)], st),
+        "btoep_read_bandwidth": ([sz, ctypes.c_int, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                  ctypes.POINTER(dbl)], st),
         "btoep_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "btoep_last_error": ([vp], ctypes.c_char_p),
     }
@@ -389,6 +391,14 @@ def btoep_apply_H(op, m, noise_prec=1.0, prior_prec=1.0, out=None, ws=None, stre
                                         wp, wn, _stream(stream)),
            "btoep_apply_H", op.handle)
     return o3[0] if squeeze else out
+
+
+def btoep_read_bandwidth(nbytes, reps=5, stream=None):
+    """Streaming-read rate of one device array of ``nbytes`` (btoep_read_bandwidth)."""
+    ms, best, mean = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().btoep_read_bandwidth(int(nbytes), int(reps), _stream(stream), ctypes.byref(ms),
+                                               ctypes.byref(best), ctypes.byref(mean)), "btoep_read_bandwidth")
+    return {"best_ms": round(ms.value, 4), "best_GBs": round(best.value, 1), "mean_GBs": round(mean.value, 1)}
 
 
 def btoep_apply_static(op, which, x, out, noise_prec=1.0, prior_prec=1.0, stream=None):

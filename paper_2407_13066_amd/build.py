@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libbtoep.so")
-SOURCES = ["api.hip", "fft.hip", "sbgemv.hip", "sbgemm.hip", "blas1.hip", "alt.hip", "sbgemm64.hip"]
+SOURCES = ["api.hip", "fft.hip", "sbgemv.hip", "sbgemm.hip", "blas1.hip", "alt.hip", "sbgemm64.hip", "calib.hip"]
 HEADERS = ["common.h", "internal.h", "blas1.h"]
 
 HIPCC_FLAGS = [

@@ -256,8 +256,9 @@ class Server:
     def idle(self):
         return not self.queue and not self.active and not self.inflight
 
-    def run(self, arrivals, t0=None, timeout=None):
-        """Drive the server through ``arrivals`` (list of (offset seconds, Request)) in real time."""
+    def run(self, arrivals, t0=None, timeout=None, progress=None):
+        """Drive the server through ``arrivals`` (list of (offset seconds, Request)) in real time.
+        ``progress(done, total)``, when given, is called every scheduling round."""
         arrivals = sorted(arrivals, key=lambda a: a[0])
         t0 = self.clock() if t0 is None else t0
         i = 0
@@ -265,6 +266,8 @@ class Server:
             now = self.clock()
             if timeout is not None and now - t0 > timeout:
                 raise TimeoutError("serving run exceeded %.1f s" % timeout)
+            if progress is not None:
+                progress(len(self.done), len(arrivals))
             while i < len(arrivals) and t0 + arrivals[i][0] <= now:
                 req = arrivals[i][1]
                 req.t_arrival = t0 + arrivals[i][0]
