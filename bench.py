@@ -210,19 +210,32 @@ def serving_benchmark(bt, n_req, rates, seed=13066, n_cap=200, check=True):
     kinds = ("F", "FT", "H", "CG")
     noise, prior, rtol = 1e4, 1e-3, 1e-6
 
+    # request inputs are read-only: every request takes k consecutive vectors of a resident pool
+    # of 32 per (operator, input type), at a random offset, so thousands of requests need no
+    # more device memory than the pool
+    npool = 32
+    pool = {}
+    for name, op in ops.items():
+        pool[(name, "m")] = torch.randn((npool, op.Nt, op.Nm), generator=gen, device="cuda")
+        pool[(name, "d")] = torch.randn((npool, op.Nt, op.Nd), generator=gen, device="cuda")
+        # inverse-problem right-hand sides b = sigma^-2 F^T y (y data vectors), in FP64
+        y = torch.randn((npool, op.Nt, op.Nd), generator=gen, device="cuda", dtype=torch.float64)
+        pool[(name, "b")] = bt.btoep_apply_FT(ops_hi[name], y).mul_(noise)
+        del y
+
     def make(rid):
         name = "ABC"[int(rng.integers(3))]
-        op = ops[name]
         kind = kinds[int(rng.integers(4))]
         k = int(rng.integers(1, 17))
-        if kind == "CG":
-            # inverse-problem right-hand side b = sigma^-2 F^T y (y a data vector), in FP64
-            y = torch.randn((k, op.Nt, op.Nd), generator=gen, device="cuda", dtype=torch.float64)
-            x = bt.btoep_apply_FT(ops_hi[name], y).mul_(noise)
-        else:
-            x = torch.randn((k, op.Nt, op.Nd if kind == "FT" else op.Nm), generator=gen, device="cuda")
+        o = int(rng.integers(0, npool - k + 1))
+        x = pool[(name, {"CG": "b", "FT": "d"}.get(kind, "m"))][o:o + k]
         return Request(rid=rid, op=name, kind=kind, x=x, noise_prec=noise, prior_prec=prior, rtol=rtol,
                        max_iter=500, inner_rtol=1e-6)
+
+    def release(done, keep=()):
+        for r in done:
+            if r not in keep:
+                r.out = None
 
     # graphs for every batch shape the server can form, captured before any timing
     ex_graph = GpuExecutor(ops, n_streams=2, max_batch=32, use_graphs=True, ops_hi=ops_hi)
@@ -275,6 +288,7 @@ def serving_benchmark(bt, n_req, rates, seed=13066, n_cap=200, check=True):
     # 10th and the 90th percentile completion, so neither the ramp-up nor the drain counts
     sat = [(0.0, make(i)) for i in range(n_cap)]
     _, done_cap, cap = run(sat, label="capacity")
+    release(done_cap)
     t_done = sorted(r.t_done for r in done_cap)
     i10, i90 = int(0.1 * len(t_done)), int(0.9 * len(t_done)) - 1
     capacity = (i90 - i10) / (t_done[i90] - t_done[i10])
@@ -297,13 +311,17 @@ def serving_benchmark(bt, n_req, rates, seed=13066, n_cap=200, check=True):
             "%.2e" % res["cg"]["max_true_rel_residual"] if "cg" in res else "-"))
         if last is None and n_req <= 400:
             # the same arrivals with batches launched kernel by kernel instead of graph replays
-            _, _, res_e = run([(t, Request(rid=r.rid, op=r.op, kind=r.kind, x=r.x, noise_prec=r.noise_prec,
-                                           prior_prec=r.prior_prec, rtol=r.rtol, max_iter=r.max_iter,
-                                           inner_rtol=r.inner_rtol)) for t, r in arrivals], ex=ex_eager,
-                              label="no graphs")
+            _, done_e, res_e = run([(t, Request(rid=r.rid, op=r.op, kind=r.kind, x=r.x, noise_prec=r.noise_prec,
+                                                prior_prec=r.prior_prec, rtol=r.rtol, max_iter=r.max_iter,
+                                                inner_rtol=r.inner_rtol)) for t, r in arrivals], ex=ex_eager,
+                                   label="no graphs")
+            release(done_e)
             out["rates"]["%.2fx_no_graphs" % frac] = res_e
             log("  same arrivals without graphs: p50 %.2f ms, p99 %.2f ms" % (res_e["p50_ms"], res_e["p99_ms"]))
+        if last is not None:
+            release(last)
         last = done
+        torch.cuda.empty_cache()
     if check:
         out["checks"] = serving_checks(bt, ops, ops_hi, last, shapes, noise, prior, rtol)
     ex_graph.close()
