@@ -107,8 +107,10 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, storages=("f32", "bf16", "f
     refs = oracle_H_columns(blocks, {"f32": [m32[c] for c in cols], "f64": [m64[c] for c in cols]})
     out = {"checked_columns": cols}
     for storage in storages:
-        if storage == "f32":
+        if storage in ("f32", "f32split"):
+            # f32split: the FP32-stored operator with its products on the BF16 matrix cores
             op = op32
+            bt.btoep_set_gemm(op, storage == "f32split")
         elif storage == "f64" and op64 is not None:
             op = op64
         else:
@@ -117,7 +119,7 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, storages=("f32", "bf16", "f
         vn = np.float64 if storage == "f64" else np.float32
         ref = refs["f64" if storage == "f64" else "f32"]
         res = {}
-        h1 = {"f32": h1_ms, "f64": h64_ms}.get(storage)
+        h1 = {"f32": h1_ms, "f32split": h1_ms, "f64": h64_ms}.get(storage)
         if h1 is None:
             # the single-vector H of this storage, the baseline of its gains
             m1 = torch.from_numpy(synth.vectors(1, Nt, Nm, synth.STREAM_M, dtype=vn)).cuda()
@@ -165,9 +167,11 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, storages=("f32", "bf16", "f
                 storage, k, ms, ms / k, h1 / (ms / k), {c: "%.1e" % e for c, e in errs.items()}))
             del M, HM, ws
             torch.cuda.empty_cache()
-        res["tolerance"] = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-3}[storage]
+        res["tolerance"] = {"f64": 1e-12, "f32": 1e-5, "f32split": 1e-5, "bf16": 3e-3}[storage]
         out[storage] = res
-        if op is not op32 and op is not op64:
+        if op is op32:
+            bt.btoep_set_gemm(op, False)
+        elif op is not op64:
             op.destroy()
     return out
 
@@ -573,9 +577,8 @@ def cg_benchmark(bt):
             sols[key] = x
             log("cg %s: %.3f s, %d inner + %d outer, true rel residual %.2e" % (
                 key, sec, r["inner_iters"], r["outer_iters"], r["rel_residual"]))
-    # BF16-stored inner operator: refinement contracts only when eps^2 * lambda_max / alpha < 1
-    # (eps ~ 2e-3 for BF16, lambda_max / alpha ~ 1e12 here), so this is expected to stall;
-    # bounded run, outcome reported as measured
+    # BF16-stored inner operator (relative storage error ~2e-3) inside FP64 refinement: a
+    # bounded run (at most 8 refinement steps of 400 inner iterations), outcome as measured
     lo16 = bt.btoep_create(synth.blocks(Nt, Nd, Nm, w["tau"]), "bf16")
     bt.btoep_autotune(lo16, reps=3)
     x = torch.zeros_like(b)
@@ -588,7 +591,7 @@ def cg_benchmark(bt):
     out["bf16_refined"] = {"status": st, "converged": bool(r["converged"]), "seconds": round(time.perf_counter() - t0, 3),
                            "inner_iters": r["inner_iters"], "outer_iters": r["outer_iters"],
                            "true_rel_residual": r["rel_residual"],
-                           "expected": "no contraction: eps^2 lambda_max / alpha >> 1 for BF16 storage"}
+                           "inner_rtol": 1e-2}
     log("cg bf16_refined: status %d, %d inner + %d outer, true rel residual %.2e" % (
         st, r["inner_iters"], r["outer_iters"], r["rel_residual"]))
     lo16.destroy()
@@ -749,7 +752,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solve measurement")
     ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape (FP64) context runs")
     ap.add_argument("--no-setup", action="store_true", help="skip the setup (block transform) measurement")
-    ap.add_argument("--multi-rhs-storage", default="f32,bf16,f64",
+    ap.add_argument("--multi-rhs-storage", default="f32,f32split,bf16,f64",
                     help="operator storages of the multi-RHS measurement (comma separated)")
     ap.add_argument("--no-appendix", action="store_true",
                     help="skip the comparison with the paper's appendix (SOTI) matvec form")

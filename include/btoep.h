@@ -316,6 +316,16 @@ btoep_status btoep_set_fft(btoep_op op, int64_t n1);
 btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma);
 
 /*
+ * Matrix-core mode of the several-right-hand-side products of an FP32-stored operator:
+ * mode 0 runs them on the FP32 matrix cores (FP32 operands); mode 1 on the BF16 matrix cores
+ * with operator and vectors each split into a BF16 high part and a BF16 remainder, keeping
+ * the three terms hi*hi + hi*lo + lo*hi (relative error of a few 1e-6 against the FP64
+ * definition, within the FP32 storage's 1e-5; the FP32 matrix cores give ~1e-6).  Single
+ * right-hand sides are unaffected.  INVALID_ARG for another mode or another storage.
+ */
+btoep_status btoep_set_gemm(btoep_op op, int mode);
+
+/*
  * Per-kernel timing for measurement: while enabled, every kernel an apply launches on this
  * operator is bracketed by HIP events recorded on the same stream.  btoep_profile_read waits
  * for the recorded events and returns, per kernel name, the launches and the summed

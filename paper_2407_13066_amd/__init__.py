@@ -99,6 +99,7 @@ def load_library(path=LIB_PATH):
                             sz, vp], st),
         "btoep_autotune": ([vp, ctypes.c_int, vp, ctypes.POINTER(TuneResult)], st),
         "btoep_set_tuning": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
+        "btoep_set_gemm": ([vp, ctypes.c_int], st),
         "btoep_set_fft": ([vp, i64], st),
         "btoep_profile_enable": ([vp, ctypes.c_int], st),
         "btoep_profile_read": ([vp, ctypes.POINTER(KernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], st),
@@ -496,6 +497,12 @@ def btoep_autotune(op, reps=5, stream=None):
 def btoep_set_fft(op, n1=0):
     """Transform mode: 0 automatic, n1 > 1 four-step with first factor n1, n1 < 0 single-pass."""
     _check(load_library().btoep_set_fft(op.handle, int(n1)), "btoep_set_fft", op.handle)
+
+
+def btoep_set_gemm(op, split):
+    """FP32 storage: several-right-hand-side products on the BF16 matrix cores with the
+    three-term split (``split`` true) or on the FP32 matrix cores."""
+    _check(load_library().btoep_set_gemm(op.handle, 1 if split else 0), "btoep_set_gemm", op.handle)
 
 
 def btoep_set_tuning(op, var_n, var_c, use_mfma=True):

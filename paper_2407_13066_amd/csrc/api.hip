@@ -36,6 +36,7 @@ struct btoep_op_s {
     void* ltw1_32 = nullptr;
     void* ltw2_32 = nullptr;
     bool gemm_enabled = true;  // MFMA kernels for several right-hand sides
+    bool gemm_split = false;   // FP32 storage: products on the BF16 matrix cores, three-term split
     int var_n = 3, var_c = 3;  // single-vector kernel variants (see sbgemv_variants)
     // the appendix (SOTI) form, kept for comparison: Fs[s][p][f] with rows of alt_ldf, the
     // matrix-sized product buffer, SOTI vector spectra and partial sums over parameter chunks
@@ -320,7 +321,7 @@ hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part,
                                ? launch_sbgemm_n64(op->fhat, op->ldF, nf, Nd, Nm, v, op->ldv, vh_b, n, pt, nspan,
                                                    part_b, st)
                                : launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, v, op->ldv, vh_b, n, pt,
-                                                 nspan, part_b, st);
+                                                 nspan, part_b, st, op->gemm_split);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -348,7 +349,8 @@ hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, i
             else if (f64)
                 e = launch_sbgemm_c64(op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st);
             else
-                e = launch_sbgemm_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st);
+                e = launch_sbgemm_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st,
+                                    op->gemm_split);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1423,6 +1425,12 @@ btoep_status btoep_alt_apply(btoep_op op, btoep_which which, int mode, const voi
                                   ldf, op->alt_chunk, op->alt_nchunk, st));
     BT_HIP(op, launch_transpose(vc, op->alt_v, ldf, 0, vh, op->ldv, 0, Nm, nf, 1, st));
     BT_HIP(op, vec_c2r(op, 1, vh, tmp, po, none, 0.0, st));
+    return BTOEP_OK;
+}
+
+btoep_status btoep_set_gemm(btoep_op op, int mode) {
+    if (!op || mode < 0 || mode > 1 || (mode == 1 && op->storage != BTOEP_F32)) return BTOEP_ERR_INVALID_ARG;
+    op->gemm_split = mode == 1;
     return BTOEP_OK;
 }
 

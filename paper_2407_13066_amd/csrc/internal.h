@@ -122,11 +122,13 @@ size_t sbgemm_c_lds(int nb, int Nd);
 // The N launcher takes at most kGemmNMax right-hand sides (an 8-tile N kernel measured slower
 // than two 4-tile launches); callers group larger batches.
 constexpr int kGemmNMax = 32;
+// `split` (FP32 storage only): run the products on the BF16 matrix cores with the operator and
+// the vectors split into BF16 high parts and remainders (three MFMAs per product).
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
-                           int nspan, int64_t part_batch, hipStream_t s);
+                           int nspan, int64_t part_batch, hipStream_t s, bool split = false);
 hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* dh, int64_t dh_batch, int nb, void* mo, int64_t ldv,
-                           int64_t mo_batch, hipStream_t s);
+                           int64_t mo_batch, hipStream_t s, bool split = false);
 
 }  // namespace btoep

@@ -20,10 +20,17 @@
 //               B operand, lanes own output columns p, so each result row of 16 p values
 //               is stored as one contiguous run; no reduction across workgroups.
 //
-// FP32 storage uses v_mfma_f32_16x16x4_f32; BF16 storage uses v_mfma_f32_16x16x32_bf16
-// with the FP32 vector operand split into a BF16 high part and a BF16 remainder (two
-// MFMAs), so the vector keeps ~16 significant bits and the result error is dominated by
-// the BF16 rounding of the stored operator.  Accumulation is FP32 in both.
+// Three product modes (template parameter MODE):
+//   kF32   FP32 storage on v_mfma_f32_16x16x4_f32 (FP32 operands);
+//   kBF16  BF16 storage on v_mfma_f32_16x16x32_bf16, with the FP32 vector operand split into a
+//          BF16 high part and a BF16 remainder (two MFMAs), so the vector keeps ~16 significant
+//          bits and the result error is dominated by the BF16 rounding of the stored operator;
+//   kSplit FP32 storage on the BF16 matrix cores: the FP32 operator is split the same way as
+//          it is loaded (hardware round-to-nearest-even conversions), and the product keeps
+//          the three terms hi*hi + hi*lo + lo*hi (three MFMAs, each ~16x the FP32 MFMA rate);
+//          the dropped lo*lo term and the remainders' rounding leave a relative error of
+//          about 2^-17 per product, averaging to a few 1e-6 over the sums.
+// Accumulation is FP32 in all three.
 //
 // MFMA 16x16 operand layout used (lane l of 64, g = l / 16, i = l % 16):
 //   A (16 x K): lane holds row i, K group g;  B (K x 16): lane holds column i, K group g;
@@ -36,7 +43,11 @@ namespace btoep {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kF32 = 0, kBF16 = 1, kSplit = 2;
 
 constexpr int kGemmThreads = 256;
 // Complex columns of the vector side staged per LDS chunk (N direction).  On wide launches the
@@ -98,6 +109,16 @@ __device__ __forceinline__ void split_bf16(float re, float im, uint32_t& hi, uin
     hi = rh | (ih << 16);
     lo = f32_to_bf16_rne(rr) | (f32_to_bf16_rne(ir) << 16);
 }
+// (re, im) of an FP32 operator entry (raw bits) as packed bf16 high parts and remainders, with
+// the packed round-to-nearest-even conversion of gfx950; the remainder re - hi is exact in FP32.
+// Returns (hi, lo).
+__device__ __forceinline__ uint2 split_bf16_hw(uint32_t re_bits, uint32_t im_bits) {
+    const f2v_t x = {__uint_as_float(re_bits), __uint_as_float(im_bits)};
+    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf2v));
+    const f2v_t r = {x[0] - __uint_as_float(hi << 16), x[1] - __uint_as_float(hi & 0xffff0000u)};
+    return uint2{hi, __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf2v))};
+}
+
 // From a packed bf16 pair (re | im << 16): (re, -im) and (im, re).
 __device__ __forceinline__ uint32_t bf_re_negim(uint32_t x) { return x ^ 0x80000000u; }
 __device__ __forceinline__ uint32_t bf_im_re(uint32_t x) { return (x >> 16) | (x << 16); }
@@ -111,12 +132,14 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // staged (8 bytes: float complex, or (hi, lo) packed bf16 pairs; row stride kChunk + 2) or,
 // with PAT, both B-operand patterns a lane can need (16 bytes, row stride kChunk + 1): lanes of
 // even result column (real part) take the first 8 bytes, lanes of odd column the second.
-template <bool BF, int NT, int kChunk>
+template <int MODE, int NT, int kChunk>
 __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
                                                            int64_t mh_batch, int nb, cx<float>* __restrict__ part,
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
     constexpr bool PAT = Patterns<NT>::value;
+    constexpr bool BF = MODE != kF32;                 // vector side staged as bf16 (hi, lo)
+    constexpr int SB = MODE == kBF16 ? 4 : 8;         // bytes of a stored operator entry
     constexpr int LDR = PAT ? kChunk + 1 : kChunk + 2;  // row stride (entries) of a staged chunk
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint2* buf = reinterpret_cast<uint2*>(smem_raw);   // [2][NT*8][LDR] 8-byte entries
@@ -180,8 +203,8 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
         const int rt0 = rg + wave * 32;  // first row of this wave's two 16-row tiles
         const bool t0 = rt0 < Nd, t1 = rt0 + 16 < Nd;
         const int s0 = min(rt0 + li, Nd - 1), s1 = min(rt0 + 16 + li, Nd - 1);
-        const char* F0 = (const char*)Fh_ + ((int64_t)f * Nd + s0) * ldF * (BF ? 4 : 8);
-        const char* F1 = (const char*)Fh_ + ((int64_t)f * Nd + s1) * ldF * (BF ? 4 : 8);
+        const char* F0 = (const char*)Fh_ + ((int64_t)f * Nd + s0) * ldF * SB;
+        const char* F1 = (const char*)Fh_ + ((int64_t)f * Nd + s1) * ldF * SB;
         f4v acc[2][NT];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -206,7 +229,7 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
                     const int q0 = ks * 16 + lg * 4;       // column within the chunk
                     const int64_t col = cb + q0;           // operator column
                     const bool in = (col < col0 + ncol);   // whole 4-column group lies past the end otherwise
-                    if (!BF) {
+                    if constexpr (!BF) {
                         float a0[8], a1[8];
                         if (in) {
                             const u32x4* p0 = (const u32x4*)(F0 + col * 8);
@@ -251,10 +274,34 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
                             }
                         }
                     } else {
+                        // A operand: 4 complex operator entries of this lane group's columns,
+                        // K order (column q, re / im); kSplit also keeps the remainders
                         u32x4 a0 = {0u, 0u, 0u, 0u}, a1 = {0u, 0u, 0u, 0u};
+                        u32x4 a0l = {0u, 0u, 0u, 0u}, a1l = {0u, 0u, 0u, 0u};
                         if (in) {
-                            a0 = *(const u32x4*)(F0 + col * 4);
-                            a1 = *(const u32x4*)(F1 + col * 4);
+                            if constexpr (MODE == kBF16) {
+                                a0 = *(const u32x4*)(F0 + col * 4);
+                                a1 = *(const u32x4*)(F1 + col * 4);
+                            } else {
+                                const u32x4* p0 = (const u32x4*)(F0 + col * 8);
+                                const u32x4* p1 = (const u32x4*)(F1 + col * 8);
+                                const u32x4 w0 = p0[0], w1 = p0[1], x0 = p1[0], x1 = p1[1];
+#pragma unroll
+                                for (int e = 0; e < 2; ++e) {
+                                    uint2 h = split_bf16_hw(w0[2 * e], w0[2 * e + 1]);
+                                    a0[e] = h.x;
+                                    a0l[e] = h.y;
+                                    h = split_bf16_hw(w1[2 * e], w1[2 * e + 1]);
+                                    a0[2 + e] = h.x;
+                                    a0l[2 + e] = h.y;
+                                    h = split_bf16_hw(x0[2 * e], x0[2 * e + 1]);
+                                    a1[e] = h.x;
+                                    a1l[e] = h.y;
+                                    h = split_bf16_hw(x1[2 * e], x1[2 * e + 1]);
+                                    a1[2 + e] = h.x;
+                                    a1l[2 + e] = h.y;
+                                }
+                            }
                         }
 #pragma unroll
                         for (int n = 0; n < NT; ++n) {
@@ -275,9 +322,11 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
                             }
                             acc[0][n] = mfma_bf16(a0, bh, acc[0][n]);
                             acc[0][n] = mfma_bf16(a0, bl, acc[0][n]);
+                            if constexpr (MODE == kSplit) acc[0][n] = mfma_bf16(a0l, bh, acc[0][n]);
                             if (t1) {
                                 acc[1][n] = mfma_bf16(a1, bh, acc[1][n]);
                                 acc[1][n] = mfma_bf16(a1, bl, acc[1][n]);
+                                if constexpr (MODE == kSplit) acc[1][n] = mfma_bf16(a1l, bh, acc[1][n]);
                             }
                         }
                     }
@@ -311,10 +360,11 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
 // p0 = 32 W blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
 // result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are
 // staged in LDS once (as the A operand pattern's source).
-template <bool BF, int NT, int W = CWaves<NT>::value>
+template <int MODE, int NT, int W = CWaves<NT>::value>
 __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ dh, int64_t dh_batch, int nb,
                                                            cx<float>* __restrict__ mo, int64_t ldv, int64_t mo_batch) {
+    constexpr bool BF = MODE != kF32;  // data spectra staged as bf16 (hi, lo)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint2* dsh = reinterpret_cast<uint2*>(smem_raw);  // [NT*8][Ndp]: float complex or (hi, lo) bf16 pairs
     const int Ndp = (Nd + 15) & ~15;
@@ -351,7 +401,7 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
         for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
 
     const int64_t frow = (int64_t)f * Nd;
-    if (!BF) {
+    if constexpr (MODE == kF32) {
         const cx<float>* Fh = (const cx<float>*)Fh_;
         // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs.  The operator loads
         // of the next kPre steps are in flight while a step runs.
@@ -396,15 +446,23 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
         }
     } else {
         const uint32_t* Fh = (const uint32_t*)Fh_;
+        const cx<float>* Fh32 = (const cx<float>*)Fh_;
         // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im)
         for (int s0 = 0; s0 < Nd; s0 += 16) {
-            u32x4 b[2];
+            u32x4 b[2], bl[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int s = s0 + 4 * lg + q;
-                    b[a][q] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
+                    if constexpr (MODE == kBF16) {
+                        b[a][q] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
+                    } else {
+                        const uint2 w = (s < Nd) ? ld_nt8(Fh32 + (frow + s) * ldF + pc[a]) : uint2{0u, 0u};
+                        const uint2 h = split_bf16_hw(w.x, w.y);
+                        b[a][q] = h.x;
+                        bl[a][q] = h.y;
+                    }
                 }
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
@@ -423,6 +481,7 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
                 for (int a = 0; a < 2; ++a) {
                     acc[a][n] = mfma_bf16(ah, b[a], acc[a][n]);
                     acc[a][n] = mfma_bf16(al, b[a], acc[a][n]);
+                    if constexpr (MODE == kSplit) acc[a][n] = mfma_bf16(ah, bl[a], acc[a][n]);
                 }
             }
         }
@@ -458,7 +517,7 @@ static int nt_of(int nb) { return nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 
 
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
-                           hipStream_t s) {
+                           hipStream_t s, bool split) {
     if (st == Stor::C128 || nb < 1 || nb > kGemmNMax) return hipErrorInvalidValue;
     const int CS = n_span_cols(st, Nm, nfreq);  // the single-vector kernel's spans (multiples of 256 columns)
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
@@ -477,18 +536,26 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
             k_sbgemm_n<BFV, NTV, Chunk<NTV, false>::value><<<grid, block, lds, s>>>(                       \
                 Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, part_batch);                   \
     } while (0)
-    const bool bf = st == Stor::BF16;
+    const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
+#define BT_GN_MODE(NTV)                     \
+    do {                                    \
+        if (mode == kBF16) BT_GN(kBF16, NTV);   \
+        else if (mode == kSplit) BT_GN(kSplit, NTV); \
+        else BT_GN(kF32, NTV);              \
+    } while (0)
     switch (NT) {
-        case 1: if (bf) BT_GN(true, 1); else BT_GN(false, 1); break;
-        case 2: if (bf) BT_GN(true, 2); else BT_GN(false, 2); break;
-        default: if (bf) BT_GN(true, 4); else BT_GN(false, 4); break;
+        case 1: BT_GN_MODE(1); break;
+        case 2: BT_GN_MODE(2); break;
+        default: BT_GN_MODE(4); break;
     }
+#undef BT_GN_MODE
 #undef BT_GN
     return hipGetLastError();
 }
 
 hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* dh,
-                           int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s) {
+                           int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s,
+                           bool split) {
     if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
     const size_t lds = sbgemm_c_lds(nb, Nd);
@@ -499,13 +566,20 @@ hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     cx<float>* o = (cx<float>*)mo;
 #define BT_GC(BFV, NTV) \
     k_sbgemm_c<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch)
-    const bool bf = st == Stor::BF16;
+    const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
+#define BT_GC_MODE(NTV)                     \
+    do {                                    \
+        if (mode == kBF16) BT_GC(kBF16, NTV);   \
+        else if (mode == kSplit) BT_GC(kSplit, NTV); \
+        else BT_GC(kF32, NTV);              \
+    } while (0)
     switch (NT) {
-        case 1: if (bf) BT_GC(true, 1); else BT_GC(false, 1); break;
-        case 2: if (bf) BT_GC(true, 2); else BT_GC(false, 2); break;
-        case 4: if (bf) BT_GC(true, 4); else BT_GC(false, 4); break;
-        default: if (bf) BT_GC(true, 8); else BT_GC(false, 8); break;
+        case 1: BT_GC_MODE(1); break;
+        case 2: BT_GC_MODE(2); break;
+        case 4: BT_GC_MODE(4); break;
+        default: BT_GC_MODE(8); break;
     }
+#undef BT_GC_MODE
 #undef BT_GC
     return hipGetLastError();
 }

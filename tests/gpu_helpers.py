@@ -8,7 +8,12 @@ def to_dev(a, dtype):
 
 
 def make(bt, blocks, storage):
-    return bt.btoep_create(np.ascontiguousarray(blocks, dtype=np.float64), storage)
+    """Operator of `storage`; "f32split" is FP32 storage whose several-right-hand-side products
+    run on the BF16 matrix cores with the three-term split."""
+    op = bt.btoep_create(np.ascontiguousarray(blocks, dtype=np.float64), "f32" if storage == "f32split" else storage)
+    if storage == "f32split":
+        bt.btoep_set_gemm(op, True)
+    return op
 
 
 def gpu_F(bt, storage):

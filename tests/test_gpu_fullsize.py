@@ -77,11 +77,13 @@ def test_full_vectors_F_FT_H(bt, blocks, op32):
     assert e_F <= 1e-5 and e_FT <= 1e-5 and e_H <= 1e-5
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f32split", 1e-5), ("bf16", 3e-3)])
 def test_multi_rhs_full_size(bt, blocks, op32, storage, tol):
     """k = 8 right-hand sides at full size; every column against the oracle."""
     print("case full-size k=8", storage, flush=True)
-    op = op32 if storage == "f32" else bt.btoep_create(blocks, "bf16")
+    op = op32 if storage == "f32" else bt.btoep_create(blocks, "bf16" if storage == "bf16" else "f32")
+    if storage == "f32split":
+        bt.btoep_set_gemm(op, True)
     k = 8
     M = synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=np.float32)
     Md = torch.from_numpy(M).cuda()
@@ -95,3 +97,27 @@ def test_multi_rhs_full_size(bt, blocks, op32, storage, tol):
         assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol
     if op is not op32:
         op.destroy()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage,tol", [("f32split", 1e-5), ("bf16", 3e-3)])
+def test_multi_rhs_full_size_k64(bt, blocks, op32, storage, tol):
+    """k = 64 right-hand sides at full size (the matrix-core kernels' widest tiles, two
+    forward launches of 32): columns 0, 31, 32 and 63 against the oracle."""
+    print("case full-size k=64", storage, flush=True)
+    op = bt.btoep_create(blocks, "bf16" if storage == "bf16" else "f32")
+    if storage == "f32split":
+        bt.btoep_set_gemm(op, True)
+    k = 64
+    M = synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=np.float32)
+    Md = torch.from_numpy(M).cuda()
+    HM = bt.btoep_apply_H(op, Md, 1.0, 1.0)
+    cols = [0, 31, 32, 63]
+    HM = HM[cols].double().cpu().numpy()
+    M64 = M[cols].astype(np.float64)
+    HM_ref = oracle.apply_H(blocks, M64, 1.0, 1.0)
+    for i in range(len(cols)):
+        e = oracle.rel_l2(HM[i], HM_ref[i])
+        print("column", cols[i], "rel l2 %.2e" % e, flush=True)
+        assert e <= tol
+    op.destroy()

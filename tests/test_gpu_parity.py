@@ -14,7 +14,7 @@ from tests.gpu_helpers import gpu_F, gpu_FT, gpu_H, make, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32split": 1e-5, "bf16": 3e-3}
 
 
 def run_all_three(bt, op, m, d, noise_prec=1.0, prior_prec=1.0):
@@ -128,7 +128,7 @@ MULTI = [((13, 7, 1000), 2), ((13, 7, 1000), 9), ((64, 100, 4099), 8), ((64, 100
 
 
 @pytest.mark.parametrize("shape,k", MULTI)
-@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32split", "bf16"])
 def test_multi_rhs_matrix_cores(bt, shape, k, storage):
     Nt, Nd, Nm = shape
     print("case multi", shape, k, storage, flush=True)
@@ -154,7 +154,7 @@ def test_multi_rhs_matrix_cores(bt, shape, k, storage):
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f32split", "bf16"])
 def test_multi_rhs_on_a_wide_launch(bt, storage):
     """Enough (span, frequency) workgroups (66 x 65) for the forward product's wide chunks of
     vector columns, with a ragged last span (Nm = 65 x 4096 + 3761)."""
@@ -176,7 +176,7 @@ def test_multi_rhs_on_a_wide_launch(bt, storage):
         assert oracle.rel_l2(HM[r], HM_ref[i]) <= tol, ("H", r)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32split", "bf16"])
 def test_matrix_core_results_are_batch_invariant(bt, storage):
     """A right-hand side gives bitwise the same result in any batch of k >= 2 and at any position."""
     rng = np.random.default_rng(41)
