@@ -39,6 +39,14 @@ struct Dft<4, DIR, T> {
         v[1] = cadd(b0, b1);
         v[3] = csub(b0, b1);
     }
+    // the same with v[2] = v[3] = 0 (the zero padding of a transform's first pass)
+    __device__ static void run_hz(cx<T>* v) {
+        const cx<T> a0 = v[0], a1 = v[1], b1 = cmul_i<DIR>(v[1]);
+        v[0] = cadd(a0, a1);
+        v[2] = csub(a0, a1);
+        v[1] = cadd(a0, b1);
+        v[3] = csub(a0, b1);
+    }
 };
 
 template <int DIR, typename T>
@@ -52,6 +60,23 @@ struct Dft<8, DIR, T> {
             b[q] = csub(v[q], v[q + 4]);
         }
         // b_q *= exp(DIR * 2 pi i q / 8)
+        b[1] = cx<T>{h * (b[1].re - DIR * b[1].im), h * (b[1].im + DIR * b[1].re)};
+        b[2] = cmul_i<DIR>(b[2]);
+        b[3] = cx<T>{h * (-b[3].re - DIR * b[3].im), h * (-b[3].im + DIR * b[3].re)};
+        Dft<4, DIR, T>::run(a);
+        Dft<4, DIR, T>::run(b);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[2 * u] = a[u];
+            v[2 * u + 1] = b[u];
+        }
+    }
+    // the same with v[4..7] = 0
+    __device__ static void run_hz(cx<T>* v) {
+        const T h = (T)0.70710678118654752440;
+        cx<T> a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = b[q] = v[q];
         b[1] = cx<T>{h * (b[1].re - DIR * b[1].im), h * (b[1].im + DIR * b[1].re)};
         b[2] = cmul_i<DIR>(b[2]);
         b[3] = cx<T>{h * (-b[3].re - DIR * b[3].im), h * (-b[3].im + DIR * b[3].re)};
@@ -208,14 +233,22 @@ struct RootTable<21> {
 // W_M = exp(DIR 2 pi i / M): N2 DFTs of size N1, the twiddles, then N1 DFTs of size N2.
 template <int N1, int N2, int DIR, typename T>
 struct DftComp {
-    __device__ static void run(cx<T>* v) {
+    __device__ static void run(cx<T>* v) { run_t<false>(v); }
+    // the same with the upper half v[N/2 ..] = 0 (N1 even: the inputs with n1 >= N1/2)
+    __device__ static void run_hz(cx<T>* v) { run_t<true>(v); }
+    template <bool HZ>
+    __device__ static void run_t(cx<T>* v) {
         constexpr int N = N1 * N2;
+        static_assert(!HZ || N1 % 2 == 0, "zero upper half needs an even first factor");
         cx<T> y[N2][N1];
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) {
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) y[n2][n1] = v[N2 * n1 + n2];
-            Dft<N1, DIR, T>::run(y[n2]);
+            if constexpr (HZ)
+                Dft<N1, DIR, T>::run_hz(y[n2]);
+            else
+                Dft<N1, DIR, T>::run(y[n2]);
 #pragma unroll
             for (int k1 = 1; k1 < N1; ++k1) {
                 if (n2 == 0) continue;
@@ -340,7 +373,9 @@ struct CtPlan {
     static constexpr int N = (Rs * ... * 1);
 };
 
-template <typename T, int R, int DIR, int CMAX, int N, int Ns, bool TWL>
+// HALF: only outputs r < (R+1)/2 of every butterfly are written -- for the last pass of an
+// inverse transform whose consumer reads only z_m, m < N/2 (there m = j + r Ns).
+template <typename T, int R, int DIR, int CMAX, int N, int Ns, bool TWL, bool HALF = false>
 __device__ __forceinline__ void ct_pass(int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const cx<T>* tw = TWL ? reinterpret_cast<const cx<T>*>(fft_smem + tw_off) : twg;
@@ -377,21 +412,29 @@ __device__ __forceinline__ void ct_pass(int logP, size_t tw_off, const cx<T>* __
             const int k = j % Ns;
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) sh[((base + r * Ns) << logP) + c] = v[bb][r];
+            for (int r = 0; r < (HALF ? (R + 1) / 2 : R); ++r) sh[((base + r * Ns) << logP) + c] = v[bb][r];
         }
     }
     __syncthreads();
 }
 
+template <typename T, int DIR, int CMAX, bool TWL, bool HALF_LAST, int N, int Ns, int R, int... Rest>
+__device__ __forceinline__ void ct_passes_h(int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
+    if constexpr (sizeof...(Rest) > 0) {
+        ct_pass<T, R, DIR, CMAX, N, Ns, TWL>(logP, tw_off, twg);
+        ct_passes_h<T, DIR, CMAX, TWL, HALF_LAST, N, Ns * R, Rest...>(logP, tw_off, twg);
+    } else {
+        ct_pass<T, R, DIR, CMAX, N, Ns, TWL, HALF_LAST>(logP, tw_off, twg);
+    }
+}
 template <typename T, int DIR, int CMAX, bool TWL, int N, int Ns, int R, int... Rest>
 __device__ __forceinline__ void ct_passes(int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
-    ct_pass<T, R, DIR, CMAX, N, Ns, TWL>(logP, tw_off, twg);
-    if constexpr (sizeof...(Rest) > 0) ct_passes<T, DIR, CMAX, TWL, N, Ns * R, Rest...>(logP, tw_off, twg);
+    ct_passes_h<T, DIR, CMAX, TWL, false, N, Ns, R, Rest...>(logP, tw_off, twg);
 }
 
-template <typename T, int DIR, int CMAX, bool TWL, int... Rs>
+template <typename T, int DIR, int CMAX, bool TWL, bool HALF_LAST = false, int... Rs>
 __device__ __forceinline__ void ct_run(CtPlan<Rs...>, int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
-    ct_passes<T, DIR, CMAX, TWL, CtPlan<Rs...>::N, 1, Rs...>(logP, tw_off, twg);
+    ct_passes_h<T, DIR, CMAX, TWL, HALF_LAST, CtPlan<Rs...>::N, 1, Rs...>(logP, tw_off, twg);
 }
 
 template <typename T>
@@ -701,6 +744,198 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     }
 }
 
+// ---- vector-side transforms with fixed column tiles (FP32, compile-time plans) ------------
+// The same transforms as k_fft_r2c / k_fft_c2r at their widest tile, with the tile width
+// 2^LOGP a compile-time constant (every index is then shifts and masks) and the two ends of
+// each transform fused with its global memory accesses; the arithmetic counts, not the
+// memory traffic, bounded the general kernels:
+//  - forward: every thread of the first pass loads its butterfly's inputs straight from the
+//    real rows (z_n = x_{2n} + i x_{2n+1}; the upper half n >= N/2 is the zero padding and is
+//    neither loaded nor added), so the input never passes through LDS; the output bins are
+//    formed in pairs f, N-f, which share both spectrum reads and the twiddle product:
+//    X_f = E + T, X_{N-f} = conj(E - T) with E = (Z_f + conj Z_{N-f}) / 2 and T = W_{2N}^f O;
+//  - inverse: the spectrum rows f and N-f are loaded into registers and split into Z_f, Z_{N-f}
+//    before the first LDS write (one LDS round trip and one barrier fewer).
+template <typename PL>
+struct FirstRadix;
+template <int R0, int... Rs>
+struct FirstRadix<CtPlan<R0, Rs...>> {
+    static constexpr int value = R0;
+};
+// The passes of a plan after its first one.
+template <typename T, int DIR, int CMAX, bool TWL, typename PL>
+struct RestPasses;
+template <typename T, int DIR, int CMAX, bool TWL, int R0, int... Rs>
+struct RestPasses<T, DIR, CMAX, TWL, CtPlan<R0, Rs...>> {
+    __device__ static void run(int logP, size_t tw_off, const cx<T>* __restrict__ twg) {
+        if constexpr (sizeof...(Rs) > 0)
+            ct_passes<T, DIR, CMAX, TWL, CtPlan<R0, Rs...>::N, R0, Rs...>(logP, tw_off, twg);
+    }
+};
+
+// Global pointers (address space 1), so that the accesses compile to global rather than flat
+// memory instructions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename PL, int LOGP>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vr2c(
+    PtrBatch in, int64_t in_row, cx<float>* __restrict__ out, int64_t out_row, int64_t out_batch, int Nt, int ncols,
+    const cx<float>* __restrict__ twg) {
+    typedef float T;
+    constexpr int N = PL::N, P = 1 << LOGP, R = FirstRadix<PL>::value, NR = N / R;
+    constexpr int RSTEP = kFftThreads >> LOGP;  // rows a thread advances per loop step
+    constexpr bool TWL = ct_twl<T>(N);
+    static_assert(R % 2 == 0 && NR * P <= kFftThreads, "one first-pass butterfly per thread");
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
+    const int col0 = column_block() << LOGP;
+    const int tid = threadIdx.x;
+    const int c = tid & (P - 1), j = tid >> LOGP;  // column; first-pass butterfly / first bin pair
+    const bool live = col0 + c < ncols;
+    const gptr<const T> xc = (gptr<const T>)static_cast<const T*>(in.at(blockIdx.y)) + min(col0 + c, ncols - 1);
+    // first pass (Ns = 1), butterfly j: inputs n = j + r NR for r < R/2, loaded from rows 2n, 2n+1
+    cx<T> v[R];
+    if (j < NR) {
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) {
+            const int n = j + r * NR;
+            v[r].re = (2 * n < Nt && live) ? xc[(int64_t)(2 * n) * in_row] : (T)0;
+            v[r].im = (2 * n + 1 < Nt && live) ? xc[(int64_t)(2 * n + 1) * in_row] : (T)0;
+        }
+    }
+    const cx<T>* tw = stage_twiddles<T>(tw_off, TWL, N, twg);
+    if (j < NR) {
+        Dft<R, -1, T>::run_hz(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) sh[((j * R + r) << LOGP) + c] = v[r];
+    }
+    __syncthreads();
+    RestPasses<T, -1, FftCfg<T>::CMAX, TWL, PL>::run(LOGP, tw_off, twg);
+    // bins in pairs (f, N - f), f = j, j + RSTEP, ... <= N/2; this thread keeps column c
+    if (!live) return;
+    const gptr<cx<T>> yc = (gptr<cx<T>>)(out + (int64_t)blockIdx.y * out_batch + col0 + c);
+    gptr<cx<T>> q0 = yc + (int64_t)j * out_row;
+    gptr<cx<T>> q1 = yc + (int64_t)(N - j) * out_row;
+    const int64_t qstep = (int64_t)RSTEP * out_row;
+    for (int f = j; f <= N / 2; f += RSTEP, q0 += qstep, q1 -= qstep) {
+        const int g = f == 0 ? 0 : N - f;
+        const cx<T> Z = sh[(f << LOGP) + c];
+        const cx<T> Zc = cconj(sh[(g << LOGP) + c]);
+        const cx<T> E = cscale(cadd(Z, Zc), (T)0.5);
+        const cx<T> O = cmul_i<-1>(cscale(csub(Z, Zc), (T)0.5));
+        const cx<T> Tw = cmul(tw[f], O);
+        const cx<T> X0 = cadd(E, Tw), X1 = cconj(csub(E, Tw));
+        if constexpr ((8 << LOGP) >= 64) {  // runs of >= 64 bytes per row: non-temporal (see put_nt)
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            __builtin_nontemporal_store(f2v{X0.re, X0.im}, (gptr<f2v>)q0);
+            if (2 * f != N) __builtin_nontemporal_store(f2v{X1.re, X1.im}, (gptr<f2v>)q1);
+        } else {
+            q0->re = X0.re;
+            q0->im = X0.im;
+            if (2 * f != N) {
+                q1->re = X1.re;
+                q1->im = X1.im;
+            }
+        }
+    }
+}
+
+template <typename PL, int LOGP>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vc2r(
+    const cx<float>* __restrict__ in, int64_t in_row, int64_t in_batch, PtrBatch out, int64_t out_row, PtrBatch add,
+    float add_scale, int Nt, int ncols, const cx<float>* __restrict__ twg, float out_scale) {
+    typedef float T;
+    constexpr int N = PL::N, P = 1 << LOGP;
+    constexpr int RSTEP = kFftThreads >> LOGP;
+    constexpr bool TWL = ct_twl<T>(N);
+    constexpr int K = (N / 2 + 1 + RSTEP - 1) / RSTEP;  // bin pairs per thread (upper bound)
+    cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
+    const T* shr = reinterpret_cast<const T*>(fft_smem);
+    const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
+    const int col0 = column_block() << LOGP;
+    const int tid = threadIdx.x;
+    const int c = tid & (P - 1), j0 = tid >> LOGP;
+    const bool live = col0 + c < ncols;
+    const int cc = min(col0 + c, ncols - 1);
+    const gptr<const cx<T>> yc = (gptr<const cx<T>>)(in + (int64_t)blockIdx.y * in_batch + cc);
+    // rows f and N - f of every pair f = j0 + u RSTEP <= N/2, all loads in flight together
+    cx<T> yf[K], yg[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int f = min(j0 + u * RSTEP, N / 2);
+        const gptr<const cx<T>> pf = yc + (int64_t)f * in_row;
+        const gptr<const cx<T>> pg = yc + (int64_t)(N - f) * in_row;
+        yf[u] = cx<T>{pf->re, pf->im};
+        yg[u] = cx<T>{pg->re, pg->im};
+    }
+    const cx<T>* tw = stage_twiddles<T>(tw_off, TWL, N, twg);
+    if (TWL) __syncthreads();  // the twiddles staged in LDS
+    // inverse split (as c2r_split): Z_f = E + i O, E = (Y_f + conj Y_g) / 2,
+    // O = (Y_f - conj Y_g) / 2 * conj(W_{2N}^f), and likewise Z_g for g = N - f (f != 0, g != f)
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int f = j0 + u * RSTEP, g = N - f;
+        if (f > N / 2) break;
+        const cx<T> Yf = live ? yf[u] : cx<T>{0, 0}, Yg = live ? yg[u] : cx<T>{0, 0};
+        {
+            const cx<T> b = cconj(Yg);
+            const cx<T> E = cscale(cadd(Yf, b), (T)0.5);
+            const cx<T> O = cmul(cscale(csub(Yf, b), (T)0.5), cconj(tw[f]));
+            sh[(f << LOGP) + c] = cadd(E, cmul_i<1>(O));
+        }
+        if (f != 0 && g != f) {
+            const cx<T> b = cconj(Yf);
+            const cx<T> E = cscale(cadd(Yg, b), (T)0.5);
+            const cx<T> O = cmul(cscale(csub(Yg, b), (T)0.5), cconj(tw[g]));
+            sh[(g << LOGP) + c] = cadd(E, cmul_i<1>(O));
+        }
+    }
+    __syncthreads();
+    // the last pass writes only z_m, m < N/2: rows j < Nt <= N of x come from those
+    ct_run<T, 1, FftCfg<T>::CMAX, TWL, true>(PL{}, LOGP, tw_off, twg);
+    // x_j = out_scale z (j even: real part, odd: imaginary part of z_{j/2}) + add_scale a_j for
+    // rows j = j0, j0 + RSTEP, ... < Nt of column c
+    if (!live) return;
+    const gptr<T> xcol = (gptr<T>)static_cast<T*>(const_cast<void*>(out.at(blockIdx.y))) + col0 + c;
+    const T* ab = static_cast<const T*>(add.at(blockIdx.y));
+    const gptr<const T> acol = (gptr<const T>)ab + col0 + c;
+    constexpr int NJ = (N + RSTEP - 1) / RSTEP;  // rows per thread, upper bound (Nt <= N)
+    for (int u0 = 0; u0 < NJ; u0 += kLoadUnroll) {
+        T av[kLoadUnroll];
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int jr = min(j0 + (u0 + u) * RSTEP, Nt - 1);
+            av[u] = ab ? acol[(int64_t)jr * out_row] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadUnroll; ++u) {
+            const int jr = j0 + (u0 + u) * RSTEP;
+            if (jr < Nt) {
+                const T v = out_scale * shr[2 * (((jr >> 1) << LOGP) + c) + (jr & 1)];
+                const T w = ab ? fma(add_scale, av[u], v) : v;
+                const gptr<T> q = xcol + (int64_t)jr * out_row;
+                if constexpr ((4 << LOGP) >= 64)
+                    __builtin_nontemporal_store(w, q);
+                else
+                    *q = w;
+            }
+        }
+    }
+}
+
+// Plans the fused kernels take at the widest tile: the forward one needs an even first radix
+// and one first-pass butterfly per thread; the inverse one takes every compile-time plan.
+template <typename PL>
+constexpr bool vec_fused_r2c() {
+    constexpr int lp = ct_log_cols<float>(PL::N);
+    return FirstRadix<PL>::value % 2 == 0 && (PL::N / FirstRadix<PL>::value) << lp <= kFftThreads;
+}
+template <typename PL>
+constexpr bool vec_fused_c2r() {
+    return true;
+}
+
 // Data side: reduce split partial sums over spans, inverse transform, keep j < Nt, scale;
 // then either store d (F) or zero-pad, forward transform and store the bins (H).  One
 // sensor (column) per workgroup, whose partial sums part[b][s][f][span] are contiguous.
@@ -877,13 +1112,26 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
     k_fft_r2c<float, float, cx<float>, PLAN><<<grid, block, lds, st>>>(in, in_row, (cx<float>*)out, out_row, \
                                                                        out_batch, Nt, ncols, plan, lp,      \
                                                                        (const cx<float>*)tw, twl, (8 << lp) >= 64)
+        // compile-time plans at their widest tile: the fused fixed-tile kernel
+#define BT_R2C_V(PLAN)                                                                                    \
+    do {                                                                                                  \
+        if constexpr (vec_fused_r2c<PLAN>()) {                                                            \
+            if (lp == ct_log_cols<float>(PLAN::N)) {                                                      \
+                k_vr2c<PLAN, ct_log_cols<float>(PLAN::N)><<<grid, block, lds, st>>>(                      \
+                    in, in_row, (cx<float>*)out, out_row, out_batch, Nt, ncols, (const cx<float>*)tw);    \
+                break;                                                                                    \
+            }                                                                                             \
+        }                                                                                                 \
+        BT_R2C(PLAN);                                                                                     \
+    } while (0)
         switch (static_plan_id(plan, r)) {
 #define BT_CASE(ID, PLAN) \
-    case ID: BT_R2C(PLAN); break;
+    case ID: BT_R2C_V(PLAN); break;
             BT_STATIC_PLANS(BT_CASE)
 #undef BT_CASE
             default: BT_R2C(RuntimePlan); break;
         }
+#undef BT_R2C_V
 #undef BT_R2C
     } else if (r == Real::F64 && ir == Real::F64 && os == Stor::C128) {
 #define BT_R2C64(PLAN)                                                                                   \
@@ -961,13 +1209,26 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
     k_fft_c2r<float, PLAN><<<grid, block, lds, st>>>((const cx<float>*)in, in_row, in_batch, out, out_row, add, \
                                                      (float)add_scale, Nt, ncols, plan, lp, (const cx<float>*)tw, \
                                                      twl, (float)out_scale, (4 << lp) >= 64)
+#define BT_C2R_V(PLAN)                                                                                     \
+    do {                                                                                                   \
+        if constexpr (vec_fused_c2r<PLAN>()) {                                                             \
+            if (lp == ct_log_cols<float>(PLAN::N)) {                                                       \
+                k_vc2r<PLAN, ct_log_cols<float>(PLAN::N)><<<grid, block, lds, st>>>(                       \
+                    (const cx<float>*)in, in_row, in_batch, out, out_row, add, (float)add_scale, Nt, ncols, \
+                    (const cx<float>*)tw, (float)out_scale);                                               \
+                break;                                                                                     \
+            }                                                                                              \
+        }                                                                                                  \
+        BT_C2R(PLAN);                                                                                      \
+    } while (0)
         switch (static_plan_id(plan, r)) {
 #define BT_CASE(ID, PLAN) \
-    case ID: BT_C2R(PLAN); break;
+    case ID: BT_C2R_V(PLAN); break;
             BT_STATIC_PLANS(BT_CASE)
 #undef BT_CASE
             default: BT_C2R(RuntimePlan); break;
         }
+#undef BT_C2R_V
 #undef BT_C2R
     } else {
 #define BT_C2R64(PLAN)                                                                                          \
