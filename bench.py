@@ -136,6 +136,13 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, storages=("f32", "bf16", "f
             log("%s storage k=1: %.2f ms per H, rel err %.2e" % (storage, h1, err1))
             del m1, o1
         for k in ks:
+            tune = None
+            if storage != "f64":
+                # matrix-core kernel variants for this k (the storage's mode as set)
+                tune = bt.btoep_autotune_gemm(op, k, allow_split=False, reps=2)
+                log("gemm autotune %s k=%d: N %s -> %d, C %s -> %d" % (
+                    storage, k, list(tune["ms_n"].values())[0], tune["var_n"], list(tune["ms_c"].values())[0],
+                    tune["var_c"]))
             M = torch.from_numpy(synth.vectors(k, Nt, Nm, synth.STREAM_M, dtype=vn)).cuda()
             HM = torch.empty_like(M)
             ws = torch.empty(bt.btoep_workspace_size(op, "H", k), dtype=torch.uint8, device="cuda")
@@ -161,6 +168,8 @@ def multi_rhs_benchmark(bt, blocks, op32, ks, h1_ms, storages=("f32", "bf16", "f
             errs = {str(c): oracle_rel(HM[c], ref[i]) for i, c in enumerate(cols) if c < k}
             res["k%d" % k] = {"ms": round(ms, 3), "ms_per_rhs": round(ms / k, 4),
                               "gain_vs_k1": round(h1 / (ms / k), 2), "products": kern, "rel_err": errs}
+            if tune is not None:
+                res["k%d" % k]["gemm_autotune"] = tune
             if storage == "bf16":
                 res["k%d" % k]["gain_vs_fp32_k1"] = round(h1_ms / (ms / k), 2)
             log("multi-RHS %s k=%d: %.2f ms (%.3f ms/RHS, x%.1f vs its k=1), rel err %s" % (

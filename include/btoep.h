@@ -326,6 +326,37 @@ btoep_status btoep_set_tuning(btoep_op op, int var_n, int var_c, int use_mfma);
 btoep_status btoep_set_gemm(btoep_op op, int mode);
 
 /*
+ * Matrix-core autotuning (several right-hand sides, FP32 or BF16 storage): the tile shapes
+ * and launch shapes of the two product kernels are chosen per right-hand-side bucket
+ * (2..8, 9..16, 17..32, 33..64) by timing every variant on this operator's own stored data
+ * for k right-hand sides, `reps` times each, on `stream`:
+ *   forward product (F): 0 right-hand sides in groups of at most 32 (four 16-column result
+ *     tiles per launch), vector chunks sized by the launch width; 1 groups of up to 64 (one
+ *     pass over the operator, eight tiles); 2 / 3 narrow (64-column) / wide chunks always;
+ *   adjoint product (F^T): 0 the default rule (4 waves below four tiles, 8 from four on);
+ *     1..4 (waves, operator K steps in flight) = (4, 0), (8, 0), (4, 1), (8, 1).
+ * With allow_split != 0 an FP32-stored operator times both modes of btoep_set_gemm and keeps
+ * the faster one for that bucket; otherwise the bucket's current mode is kept and timed.  The fastest choice is kept for
+ * later applies in that bucket; btoep_set_gemm_variants pins one.  Every variant computes the
+ * same products (same per-right-hand-side arithmetic order within a mode).  Uses the
+ * operator's own workspace (grown with hipMalloc when needed; synchronises the device).
+ * Errors: INVALID_ARG (k outside 2..BTOEP_MAX_BATCH, reps < 1, variants out of range),
+ * UNSUPPORTED (FP64 storage, or matrix cores disabled by btoep_set_tuning), HIP.
+ */
+typedef struct {
+    int k;
+    int nvar_n, nvar_c;   /* variants timed */
+    int var_n, var_c;     /* chosen */
+    int split;            /* chosen mode (1: BF16 matrix cores, three-term split)   */
+    double ms_n[2][8];    /* [mode][variant] ms per forward product of k vectors    */
+    double ms_c[2][8];    /* [mode][variant] ms per adjoint product of k vectors    */
+} btoep_gemm_tune_result;
+
+btoep_status btoep_autotune_gemm(btoep_op op, int64_t k, int allow_split, int reps, void* stream,
+                                 btoep_gemm_tune_result* out);
+btoep_status btoep_set_gemm_variants(btoep_op op, int64_t k, int var_n, int var_c);
+
+/*
  * Per-kernel timing for measurement: while enabled, every kernel an apply launches on this
  * operator is bracketed by HIP events recorded on the same stream.  btoep_profile_read waits
  * for the recorded events and returns, per kernel name, the launches and the summed

@@ -65,6 +65,12 @@ class TuneResult(ctypes.Structure):
                 ("ms_fft", ctypes.c_double * 2)]
 
 
+class GemmTuneResult(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("nvar_n", ctypes.c_int), ("nvar_c", ctypes.c_int), ("var_n", ctypes.c_int),
+                ("var_c", ctypes.c_int), ("split", ctypes.c_int), ("ms_n", (ctypes.c_double * 8) * 2),
+                ("ms_c", (ctypes.c_double * 8) * 2)]
+
+
 def load_library(path=LIB_PATH):
     """Load libbtoep.so (raises OSError when it is missing or unloadable)."""
     global _lib
@@ -100,6 +106,8 @@ def load_library(path=LIB_PATH):
         "btoep_autotune": ([vp, ctypes.c_int, vp, ctypes.POINTER(TuneResult)], st),
         "btoep_set_tuning": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], st),
         "btoep_set_gemm": ([vp, ctypes.c_int], st),
+        "btoep_set_gemm_variants": ([vp, i64, ctypes.c_int, ctypes.c_int], st),
+        "btoep_autotune_gemm": ([vp, i64, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(GemmTuneResult)], st),
         "btoep_set_fft": ([vp, i64], st),
         "btoep_profile_enable": ([vp, ctypes.c_int], st),
         "btoep_profile_read": ([vp, ctypes.POINTER(KernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], st),
@@ -503,6 +511,28 @@ def btoep_set_gemm(op, split):
     """FP32 storage: several-right-hand-side products on the BF16 matrix cores with the
     three-term split (``split`` true) or on the FP32 matrix cores."""
     _check(load_library().btoep_set_gemm(op.handle, 1 if split else 0), "btoep_set_gemm", op.handle)
+
+
+def btoep_set_gemm_variants(op, k, var_n, var_c):
+    """Pin the matrix-core kernel variants used for k right-hand sides (its bucket)."""
+    _check(load_library().btoep_set_gemm_variants(op.handle, int(k), int(var_n), int(var_c)),
+           "btoep_set_gemm_variants", op.handle)
+
+
+def btoep_autotune_gemm(op, k, allow_split=True, reps=3, stream=None):
+    """Time the matrix-core kernel variants (and, for FP32 storage with ``allow_split``, the
+    BF16-matrix-core mode) for k right-hand sides and keep the fastest for k's bucket.
+
+    Returns {"k", "var_n", "var_c", "split", "ms_n": [[mode 0 ...], [mode 1 ...]], "ms_c": ...}."""
+    r = GemmTuneResult()
+    _check(load_library().btoep_autotune_gemm(op.handle, int(k), 1 if allow_split else 0, int(reps),
+                                              _stream(stream), ctypes.byref(r)), "btoep_autotune_gemm", op.handle)
+    modes = [0, 1] if (allow_split and op.storage == "f32") else [int(r.split)]
+    return {"k": r.k, "var_n": r.var_n, "var_c": r.var_c, "split": bool(r.split),
+            "ms_n": {("split" if m else "fp32" if op.storage == "f32" else "bf16"):
+                     [round(r.ms_n[m][v], 4) for v in range(r.nvar_n)] for m in modes},
+            "ms_c": {("split" if m else "fp32" if op.storage == "f32" else "bf16"):
+                     [round(r.ms_c[m][v], 4) for v in range(r.nvar_c)] for m in modes}}
 
 
 def btoep_set_tuning(op, var_n, var_c, use_mfma=True):

@@ -36,7 +36,11 @@ struct btoep_op_s {
     void* ltw1_32 = nullptr;
     void* ltw2_32 = nullptr;
     bool gemm_enabled = true;  // MFMA kernels for several right-hand sides
-    bool gemm_split = false;   // FP32 storage: products on the BF16 matrix cores, three-term split
+    // per right-hand-side bucket (2..8, 9..16, 17..32, 33..64): matrix-core kernel variants and,
+    // for FP32 storage, products on the BF16 matrix cores with the three-term split
+    int gvar_n[4] = {0, 0, 0, 0};
+    int gvar_c[4] = {0, 0, 0, 0};
+    bool gsplit[4] = {false, false, false, false};
     int var_n = 3, var_c = 3;  // single-vector kernel variants (see sbgemv_variants)
     // the appendix (SOTI) form, kept for comparison: Fs[s][p][f] with rows of alt_ldf, the
     // matrix-sized product buffer, SOTI vector spectra and partial sums over parameter chunks
@@ -303,14 +307,19 @@ Stor vstor(const btoep_op op) { return op->vreal == Real::F64 ? Stor::C128 : Sto
 // Per-frequency products: one vector per launch row (GEMV kernels) for a single right-hand
 // side or FP64 storage; the MFMA kernels for nb >= 2 on FP32 / BF16 storage.
 bool use_gemm(const btoep_op op, int nb) { return nb >= 2 && op->gemm_enabled; }
+// Right-hand-side bucket of the matrix-core tuning: 2..8 -> 0, 9..16 -> 1, 17..32 -> 2, 33..64 -> 3.
+int gemm_bucket(int nb) { return nb <= 8 ? 0 : (nb <= 16 ? 1 : (nb <= 32 ? 2 : 3)); }
 
 hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part, int nspan, int64_t part_b,
                   hipStream_t st) {
     const int Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
     if (use_gemm(op, nb)) {
-        // groups of at most kGemmNMax right-hand sides, balanced so that every group keeps >= 2
-        // and runs on the matrix cores
-        const int ng = (nb + kGemmNMax - 1) / kGemmNMax;
+        // groups of at most the variant's group size (FP64: kGemmNMax), balanced so that every
+        // group keeps >= 2 and runs on the matrix cores
+        const int bk = gemm_bucket(nb);
+        const int var = op->gvar_n[bk];
+        const int gmax = op->stor == Stor::C128 ? kGemmNMax : sbgemm_n_group(var);
+        const int ng = (nb + gmax - 1) / gmax;
         const int g = (nb + ng - 1) / ng;
         const size_t cb = 2 * vbytes(op);  // bytes of a vector-side complex value
         for (int r0 = 0; r0 < nb; r0 += g) {
@@ -321,7 +330,7 @@ hipError_t prod_n(btoep_op op, int nb, const void* vh, int64_t vh_b, void* part,
                                ? launch_sbgemm_n64(op->fhat, op->ldF, nf, Nd, Nm, v, op->ldv, vh_b, n, pt, nspan,
                                                    part_b, st)
                                : launch_sbgemm_n(op->stor, op->fhat, op->ldF, nf, Nd, Nm, v, op->ldv, vh_b, n, pt,
-                                                 nspan, part_b, st, op->gemm_split);
+                                                 nspan, part_b, st, op->gsplit[bk], var);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -350,7 +359,7 @@ hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, i
                 e = launch_sbgemm_c64(op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st);
             else
                 e = launch_sbgemm_c(op->stor, op->fhat, op->ldF, nf, Nd, Nm, d, dh_b, n, o, op->ldv, vh_b, st,
-                                    op->gemm_split);
+                                    op->gsplit[gemm_bucket(nb)], op->gvar_c[gemm_bucket(nb)]);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1430,7 +1439,100 @@ btoep_status btoep_alt_apply(btoep_op op, btoep_which which, int mode, const voi
 
 btoep_status btoep_set_gemm(btoep_op op, int mode) {
     if (!op || mode < 0 || mode > 1 || (mode == 1 && op->storage != BTOEP_F32)) return BTOEP_ERR_INVALID_ARG;
-    op->gemm_split = mode == 1;
+    for (bool& b : op->gsplit) b = mode == 1;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_set_gemm_variants(btoep_op op, int64_t k, int var_n, int var_c) {
+    if (!op || k < 2 || k > kMaxBatch || op->storage == BTOEP_F64) return BTOEP_ERR_INVALID_ARG;
+    if (var_n < 0 || var_n >= sbgemm_n_variants() || var_c < 0 || var_c >= sbgemm_c_variants())
+        return BTOEP_ERR_INVALID_ARG;
+    op->gvar_n[gemm_bucket((int)k)] = var_n;
+    op->gvar_c[gemm_bucket((int)k)] = var_c;
+    return BTOEP_OK;
+}
+
+btoep_status btoep_autotune_gemm(btoep_op op, int64_t k, int allow_split, int reps, void* stream,
+                                 btoep_gemm_tune_result* out) {
+    if (!op || !out || k < 2 || k > kMaxBatch || reps < 1) return BTOEP_ERR_INVALID_ARG;
+    if (op->storage == BTOEP_F64 || !op->gemm_enabled) return BTOEP_ERR_UNSUPPORTED;
+    const int nb = (int)k, bk = gemm_bucket(nb);
+    const ApplyWs w = apply_layout(op, BTOEP_APPLY_H, nb);
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    btoep_status s = get_ws(op, w.total, ws, ws_bytes);
+    if (s != BTOEP_OK) return s;
+    DeviceGuard g(op->device);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    const int nspan = (int)nspan_of(op);
+    const int64_t vh_b = op->nfreq * op->ldv, part_b = op->nfreq * nspan * op->Nd, dh_b = op->nfreq * op->Nd;
+    // defined (zero) inputs for the timing runs, written by a kernel
+    BT_HIP(op, launch_zero(Real::F32, base, (int64_t)(w.total / 4), st));
+    hipEvent_t a = nullptr, b = nullptr;
+    BT_HIP(op, hipEventCreate(&a));
+    BT_HIP(op, hipEventCreate(&b));
+    memset(out, 0, sizeof(*out));
+    out->k = nb;
+    out->nvar_n = std::min(sbgemm_n_variants(), 8);
+    out->nvar_c = std::min(sbgemm_c_variants(), 8);
+    const int nmode = (op->storage == BTOEP_F32 && allow_split) ? 2 : 1;
+    const int saved_n = op->gvar_n[bk], saved_c = op->gvar_c[bk];
+    const bool saved_split = op->gsplit[bk];
+    double best_n[2] = {1e30, 1e30}, best_c[2] = {1e30, 1e30};
+    int arg_n[2] = {0, 0}, arg_c[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    // modes timed: both when allowed, else the bucket's current one
+    for (int mi = 0; mi < nmode && e == hipSuccess; ++mi) {
+        const int mode = nmode == 2 ? mi : (saved_split ? 1 : 0);
+        op->gsplit[bk] = mode == 1;
+        for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+            const int nv = dir == 0 ? out->nvar_n : out->nvar_c;
+            for (int v = 0; v < nv && e == hipSuccess; ++v) {
+                if (dir == 0)
+                    op->gvar_n[bk] = v;
+                else
+                    op->gvar_c[bk] = v;
+                auto launch = [&]() {
+                    return dir == 0 ? prod_n(op, nb, base + w.vh, vh_b, base + w.part, nspan, part_b, st)
+                                    : prod_c(op, nb, base + w.dh, dh_b, base + w.vh, vh_b, st);
+                };
+                e = launch();
+                if (e == hipSuccess) e = hipEventRecord(a, st);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+                if (e == hipSuccess) e = hipEventRecord(b, st);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                const double per = (double)ms / reps;
+                if (dir == 0) {
+                    out->ms_n[mode][v] = per;
+                    if (per < best_n[mode]) best_n[mode] = per, arg_n[mode] = v;
+                } else {
+                    out->ms_c[mode][v] = per;
+                    if (per < best_c[mode]) best_c[mode] = per, arg_c[mode] = v;
+                }
+            }
+            if (dir == 0)
+                op->gvar_n[bk] = saved_n;
+            else
+                op->gvar_c[bk] = saved_c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    op->gsplit[bk] = saved_split;
+    if (e != hipSuccess) {
+        set_err(op, "autotune_gemm", e);
+        return BTOEP_ERR_HIP;
+    }
+    const int m = nmode == 2 ? (best_n[1] + best_c[1] < best_n[0] + best_c[0] ? 1 : 0) : (saved_split ? 1 : 0);
+    out->split = m;
+    out->var_n = arg_n[m];
+    out->var_c = arg_c[m];
+    op->gsplit[bk] = m == 1;
+    op->gvar_n[bk] = out->var_n;
+    op->gvar_c[bk] = out->var_c;
     return BTOEP_OK;
 }
 

@@ -124,11 +124,17 @@ size_t sbgemm_c_lds(int nb, int Nd);
 constexpr int kGemmNMax = 32;
 // `split` (FP32 storage only): run the products on the BF16 matrix cores with the operator and
 // the vectors split into BF16 high parts and remainders (three MFMAs per product).
+// `var` selects a tuning variant of each kernel (0 .. sbgemm_n_variants() - 1 and
+// 0 .. sbgemm_c_variants() - 1; 0 is the default rule); the N launcher takes at most
+// sbgemm_n_group(var) right-hand sides.
+int sbgemm_n_variants();
+int sbgemm_c_variants();
+int sbgemm_n_group(int var);
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* mh, int64_t ldv, int64_t mh_batch, int nb, void* part,
-                           int nspan, int64_t part_batch, hipStream_t s, bool split = false);
+                           int nspan, int64_t part_batch, hipStream_t s, bool split = false, int var = 0);
 hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm,
                            const void* dh, int64_t dh_batch, int nb, void* mo, int64_t ldv,
-                           int64_t mo_batch, hipStream_t s, bool split = false);
+                           int64_t mo_batch, hipStream_t s, bool split = false, int var = 0);
 
 }  // namespace btoep

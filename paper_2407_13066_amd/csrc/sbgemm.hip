@@ -360,7 +360,9 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
 // p0 = 32 W blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
 // result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are
 // staged in LDS once (as the A operand pattern's source).
-template <int MODE, int NT, int W = CWaves<NT>::value>
+// PF (BF16 and split modes): 1 issues the operator loads of the next K step before the current
+// step's matrix-core work, so one more step of the operator stream is in flight per wave.
+template <int MODE, int NT, int W, int PF>
 __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ dh, int64_t dh_batch, int nb,
                                                            cx<float>* __restrict__ mo, int64_t ldv, int64_t mo_batch) {
@@ -447,19 +449,44 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
     } else {
         const uint32_t* Fh = (const uint32_t*)Fh_;
         const cx<float>* Fh32 = (const cx<float>*)Fh_;
-        // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im)
-        for (int s0 = 0; s0 < Nd; s0 += 16) {
-            u32x4 b[2], bl[2];
+        // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im).
+        // Raw operator words of one step: a bf16 pair, or the FP32 (re, im) (split when used).
+        constexpr int WPE = MODE == kSplit ? 2 : 1;
+        struct Raw {
+            uint32_t w[2][4][WPE];
+        };
+        auto load_step = [&](int s0, Raw& raw) {
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int s = s0 + 4 * lg + q;
                     if constexpr (MODE == kBF16) {
-                        b[a][q] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
+                        raw.w[a][q][0] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
                     } else {
                         const uint2 w = (s < Nd) ? ld_nt8(Fh32 + (frow + s) * ldF + pc[a]) : uint2{0u, 0u};
-                        const uint2 h = split_bf16_hw(w.x, w.y);
+                        raw.w[a][q][0] = w.x;
+                        raw.w[a][q][WPE - 1] = w.y;
+                    }
+                }
+        };
+        Raw cur, nxt;
+        if constexpr (PF > 0) load_step(0, cur);
+        for (int s0 = 0; s0 < Nd; s0 += 16) {
+            if constexpr (PF > 0) {
+                if (s0 + 16 < Nd) load_step(s0 + 16, nxt);
+            } else {
+                load_step(s0, cur);
+            }
+            u32x4 b[2], bl[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (MODE == kBF16) {
+                        b[a][q] = cur.w[a][q][0];
+                    } else {
+                        const uint2 h = split_bf16_hw(cur.w[a][q][0], cur.w[a][q][WPE - 1]);
                         b[a][q] = h.x;
                         bl[a][q] = h.y;
                     }
@@ -484,6 +511,7 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
                     if constexpr (MODE == kSplit) acc[a][n] = mfma_bf16(ah, bl[a], acc[a][n]);
                 }
             }
+            if constexpr (PF > 0) cur = nxt;
         }
     }
     // C[4 lg + v][li]: result row 4 lg + v -> rhs n*8 + 2 lg + v/2, part v&1; column p = tile + li
@@ -515,14 +543,21 @@ size_t sbgemm_c_lds(int nb, int Nd) {
 
 static int nt_of(int nb) { return nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8)); }
 
+// Variants of the N kernel: 0 the default (right-hand sides in groups of at most kGemmNMax,
+// wide chunks on launches of >= kWideGrid workgroups), 1 groups of up to 64 (one pass over
+// the operator for up to 64 right-hand sides, eight-tile kernel), 2 / 3 narrow / wide chunks
+// on every launch.
+int sbgemm_n_variants() { return 4; }
+int sbgemm_n_group(int var) { return var == 1 ? kMaxBatch : kGemmNMax; }
+
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
-                           hipStream_t s, bool split) {
-    if (st == Stor::C128 || nb < 1 || nb > kGemmNMax) return hipErrorInvalidValue;
+                           hipStream_t s, bool split, int var) {
+    if (st == Stor::C128 || nb < 1 || nb > sbgemm_n_group(var)) return hipErrorInvalidValue;
     const int CS = n_span_cols(st, Nm, nfreq);  // the single-vector kernel's spans (multiples of 256 columns)
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
-    const bool wide = (int64_t)nspan * nfreq >= kWideGrid;
+    const bool wide = var == 2 ? false : (var == 3 ? true : (int64_t)nspan * nfreq >= kWideGrid);
     const size_t lds = sbgemm_n_lds(NT, chunk_of(NT, wide));
     dim3 grid(nspan, nfreq), block(kGemmThreads);
     const cx<float>* m = (const cx<float>*)mh;
@@ -546,26 +581,47 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     switch (NT) {
         case 1: BT_GN_MODE(1); break;
         case 2: BT_GN_MODE(2); break;
-        default: BT_GN_MODE(4); break;
+        case 4: BT_GN_MODE(4); break;
+        default: BT_GN_MODE(8); break;
     }
 #undef BT_GN_MODE
 #undef BT_GN
     return hipGetLastError();
 }
 
+// Variants of the C kernel (waves per workgroup, steps of operator loads in flight): 0 is the
+// default rule (4 waves below four tiles, 8 from four on; no extra step), 1..4 fix (W, PF).
+static void c_variant(int var, int NT, int& W, int& PF) {
+    static const int tab[5][2] = {{0, 0}, {4, 0}, {8, 0}, {4, 1}, {8, 1}};
+    const int v = (var >= 0 && var < 5) ? var : 0;
+    W = tab[v][0] ? tab[v][0] : (NT >= 4 ? CWaves<4>::value : CWaves<1>::value);
+    PF = tab[v][1];
+}
+int sbgemm_c_variants() { return 5; }
+
 hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* dh,
                            int64_t dh_batch, int nb, void* mo, int64_t ldv, int64_t mo_batch, hipStream_t s,
-                           bool split) {
+                           bool split, int var) {
     if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
     const size_t lds = sbgemm_c_lds(nb, Nd);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
-    const int W = NT >= 4 ? CWaves<4>::value : CWaves<1>::value;
+    int W, PF;
+    c_variant(var, NT, W, PF);
     dim3 grid((unsigned)((Nm + 32 * W - 1) / (32 * W)), nfreq), block(64 * W);
     const cx<float>* d = (const cx<float>*)dh;
     cx<float>* o = (cx<float>*)mo;
-#define BT_GC(BFV, NTV) \
-    k_sbgemm_c<BFV, NTV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch)
+#define BT_GC(BFV, NTV)                                                                                          \
+    do {                                                                                                         \
+        if (W == 4 && PF == 0)                                                                                   \
+            k_sbgemm_c<BFV, NTV, 4, 0><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
+        else if (W == 4)                                                                                         \
+            k_sbgemm_c<BFV, NTV, 4, 1><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
+        else if (PF == 0)                                                                                        \
+            k_sbgemm_c<BFV, NTV, 8, 0><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
+        else                                                                                                     \
+            k_sbgemm_c<BFV, NTV, 8, 1><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
+    } while (0)
     const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
 #define BT_GC_MODE(NTV)                     \
     do {                                    \

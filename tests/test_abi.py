@@ -144,3 +144,9 @@ def test_stepwise_cg_arguments_rejected(lib):
     ready = ctypes.c_int()
     assert lib.btoep_cg_report(None, ctypes.byref(ready), None) == 1
     assert lib.btoep_cg_end(None) == 1
+
+
+def test_gemm_tuning_arguments_rejected(lib):
+    assert lib.btoep_set_gemm(None, 0) == 1
+    assert lib.btoep_set_gemm_variants(None, 8, 0, 0) == 1
+    assert lib.btoep_autotune_gemm(None, 8, 1, 3, None, None) == 1

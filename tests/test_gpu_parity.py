@@ -298,3 +298,40 @@ def test_extreme_sensor_and_parameter_counts(bt, shape, storage, k):
     with pytest.raises(bt.BtoepError) as e:
         bt.btoep_create(np.zeros((2, 65536, 1)), storage)
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32split", "bf16"])
+def test_every_matrix_core_variant_and_gemm_autotune(bt, storage):
+    """Every forward and adjoint matrix-core kernel variant, in every right-hand-side bucket
+    (k = 9, 33 and 64 with ragged tiles; Nd past one 16-row tile group, ragged Nm), against the
+    oracle; then the matrix-core autotuner's choice."""
+    rng = np.random.default_rng(81)
+    Nt, Nd, Nm = 11, 37, 1300
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / 3.0)[:, None, None]
+    op = make(bt, blocks, storage)
+    tol = TOL[storage]
+    for k in (9, 33, 64):
+        print("case gemm variants", storage, k, flush=True)
+        M = rng.standard_normal((k, Nt, Nm)).astype(np.float32)
+        D = rng.standard_normal((k, Nt, Nd)).astype(np.float32)
+        Md, Dd = to_dev(M, torch.float32), to_dev(D, torch.float32)
+        FM_ref = oracle.apply_F(blocks, M.astype(np.float64))
+        FTD_ref = oracle.apply_FT(blocks, D.astype(np.float64))
+        combos = [(v, 0) for v in range(4)] + [(0, v) for v in range(1, 5)]
+        for var_n, var_c in combos:
+            bt.btoep_set_gemm_variants(op, k, var_n, var_c)
+            FM = bt.btoep_apply_F(op, Md).double().cpu().numpy()
+            FTD = bt.btoep_apply_FT(op, Dd).double().cpu().numpy()
+            for r in range(k):
+                assert oracle.rel_l2(FM[r], FM_ref[r]) <= tol, ("F", k, var_n, r)
+                assert oracle.rel_l2(FTD[r], FTD_ref[r]) <= tol, ("FT", k, var_c, r)
+        tune = bt.btoep_autotune_gemm(op, k, allow_split=(storage == "f32split"), reps=2)
+        assert 0 <= tune["var_n"] < 4 and 0 <= tune["var_c"] < 5
+        HM = bt.btoep_apply_H(op, Md, 1.5, 0.75).double().cpu().numpy()
+        HM_ref = oracle.apply_H(blocks, M[:3].astype(np.float64), 1.5, 0.75)
+        for r in range(3):
+            assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol, ("H after autotune", k, tune)
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_set_gemm_variants(op, 9, 4, 0)   # no such forward variant
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_set_gemm_variants(op, 1, 0, 0)   # one right-hand side has no matrix-core product
