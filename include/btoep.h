@@ -38,7 +38,16 @@ extern "C" {
 
 typedef struct btoep_op_s* btoep_op;
 
-typedef enum {
+/* The enumerations are int-sized.  C++ translation units (the library itself) see them with
+ * the fixed underlying type int, so that any int a C caller passes -- valid or not -- is a
+ * value of the type and is rejected by the argument checks instead of being undefined. */
+#ifdef __cplusplus
+#define BTOEP_ENUM enum : int
+#else
+#define BTOEP_ENUM enum
+#endif
+
+typedef BTOEP_ENUM {
     BTOEP_OK = 0,
     BTOEP_ERR_INVALID_ARG = 1,
     BTOEP_ERR_OUT_OF_MEMORY = 2,
@@ -50,13 +59,13 @@ typedef enum {
 } btoep_status;
 
 /* Storage precision of the Fourier-space operator (complex FP64, FP32 or BF16 parts). */
-typedef enum { BTOEP_F64 = 0, BTOEP_F32 = 1, BTOEP_BF16 = 2 } btoep_dtype;
+typedef BTOEP_ENUM { BTOEP_F64 = 0, BTOEP_F32 = 1, BTOEP_BF16 = 2 } btoep_dtype;
 
 /* Where an input given to btoep_create lives. */
-typedef enum { BTOEP_HOST = 0, BTOEP_DEVICE = 1 } btoep_memory;
+typedef BTOEP_ENUM { BTOEP_HOST = 0, BTOEP_DEVICE = 1 } btoep_memory;
 
 /* Operation selector for btoep_workspace_size and btoep_apply_batched. */
-typedef enum { BTOEP_APPLY_F = 0, BTOEP_APPLY_FT = 1, BTOEP_APPLY_H = 2, BTOEP_CG = 3 } btoep_which;
+typedef BTOEP_ENUM { BTOEP_APPLY_F = 0, BTOEP_APPLY_FT = 1, BTOEP_APPLY_H = 2, BTOEP_CG = 3 } btoep_which;
 
 /* Largest number of right-hand sides one btoep_apply_batched call accepts. */
 #define BTOEP_MAX_BATCH 64
@@ -113,7 +122,7 @@ btoep_status btoep_create(int64_t Nt, int64_t Nd, int64_t Nm, const double* bloc
  * Errors: INVALID_ARG (rectangle outside the operator, bad strides or enums, null
  * pointers), OUT_OF_MEMORY, HIP.
  */
-typedef enum { BTOEP_BLOCK_COLUMN = 0, BTOEP_LAST_BLOCK_ROW = 1 } btoep_block_order;
+typedef BTOEP_ENUM { BTOEP_BLOCK_COLUMN = 0, BTOEP_LAST_BLOCK_ROW = 1 } btoep_block_order;
 
 btoep_status btoep_create_empty(int64_t Nt, int64_t Nd, int64_t Nm, btoep_dtype storage, void* stream,
                                 btoep_op* out);
