@@ -869,6 +869,19 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
         yf[u] = cx<T>{pf->re, pf->im};
         yg[u] = cx<T>{pg->re, pg->im};
     }
+    // the addend (the prior term of H) of every output row this thread writes, loaded now so
+    // that its latency hides behind the transform
+    constexpr int NJ = (N + RSTEP - 1) / RSTEP;  // rows per thread, upper bound (Nt <= N)
+    const T* ab = static_cast<const T*>(add.at(blockIdx.y));
+    T av[NJ];
+    {
+        const gptr<const T> acol = (gptr<const T>)ab + cc;
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) {
+            const int jr = min(j0 + u * RSTEP, Nt - 1);
+            av[u] = ab ? acol[(int64_t)jr * out_row] : (T)0;
+        }
+    }
     const cx<T>* tw = stage_twiddles<T>(tw_off, TWL, N, twg);
     if (TWL) __syncthreads();  // the twiddles staged in LDS
     // inverse split (as c2r_split): Z_f = E + i O, E = (Y_f + conj Y_g) / 2,
@@ -898,28 +911,17 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     // rows j = j0, j0 + RSTEP, ... < Nt of column c
     if (!live) return;
     const gptr<T> xcol = (gptr<T>)static_cast<T*>(const_cast<void*>(out.at(blockIdx.y))) + col0 + c;
-    const T* ab = static_cast<const T*>(add.at(blockIdx.y));
-    const gptr<const T> acol = (gptr<const T>)ab + col0 + c;
-    constexpr int NJ = (N + RSTEP - 1) / RSTEP;  // rows per thread, upper bound (Nt <= N)
-    for (int u0 = 0; u0 < NJ; u0 += kLoadUnroll) {
-        T av[kLoadUnroll];
 #pragma unroll
-        for (int u = 0; u < kLoadUnroll; ++u) {
-            const int jr = min(j0 + (u0 + u) * RSTEP, Nt - 1);
-            av[u] = ab ? acol[(int64_t)jr * out_row] : (T)0;
-        }
-#pragma unroll
-        for (int u = 0; u < kLoadUnroll; ++u) {
-            const int jr = j0 + (u0 + u) * RSTEP;
-            if (jr < Nt) {
-                const T v = out_scale * shr[2 * (((jr >> 1) << LOGP) + c) + (jr & 1)];
-                const T w = ab ? fma(add_scale, av[u], v) : v;
-                const gptr<T> q = xcol + (int64_t)jr * out_row;
-                if constexpr ((4 << LOGP) >= 64)
-                    __builtin_nontemporal_store(w, q);
-                else
-                    *q = w;
-            }
+    for (int u = 0; u < NJ; ++u) {
+        const int jr = j0 + u * RSTEP;
+        if (jr < Nt) {
+            const T v = out_scale * shr[2 * (((jr >> 1) << LOGP) + c) + (jr & 1)];
+            const T w = ab ? fma(add_scale, av[u], v) : v;
+            const gptr<T> q = xcol + (int64_t)jr * out_row;
+            if constexpr ((4 << LOGP) >= 64)
+                __builtin_nontemporal_store(w, q);
+            else
+                *q = w;
         }
     }
 }

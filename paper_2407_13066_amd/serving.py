@@ -101,6 +101,7 @@ class Server:
         self._rr = 0
         self.rhs_applies = collections.Counter()   # right-hand-side applications per pipeline
         self.launches = 0
+        self._on_done = None
 
     # -- arrivals and admission -------------------------------------------------------------
     def submit(self, req):
@@ -131,6 +132,8 @@ class Server:
         self.used -= req.nbytes
         self.active.remove(req)
         self.done.append(req)
+        if self._on_done is not None:
+            self._on_done(req)
 
     # -- CG progress ------------------------------------------------------------------------
     def _cg_landed(self, req):
@@ -256,9 +259,11 @@ class Server:
     def idle(self):
         return not self.queue and not self.active and not self.inflight
 
-    def run(self, arrivals, t0=None, timeout=None, progress=None):
+    def run(self, arrivals, t0=None, timeout=None, progress=None, on_done=None):
         """Drive the server through ``arrivals`` (list of (offset seconds, Request)) in real time.
-        ``progress(done, total)``, when given, is called every scheduling round."""
+        ``progress(done, total)``, when given, is called every scheduling round; ``on_done(req)``
+        as each request completes (a caller that keeps only some answers drops the rest there)."""
+        self._on_done = on_done
         arrivals = sorted(arrivals, key=lambda a: a[0])
         t0 = self.clock() if t0 is None else t0
         i = 0
