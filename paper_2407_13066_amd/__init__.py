@@ -523,12 +523,14 @@ def btoep_autotune_gemm(op, k, allow_split=True, reps=3, stream=None):
     """Time the matrix-core kernel variants (and, for FP32 storage with ``allow_split``, the
     BF16-matrix-core mode) for k right-hand sides and keep the fastest for k's bucket.
 
-    Returns {"k", "var_n", "var_c", "split", "ms_n": [[mode 0 ...], [mode 1 ...]], "ms_c": ...}."""
+    Returns {"k", "nvar_n", "nvar_c", "var_n", "var_c", "split", "ms_n": {mode: [ms per variant]},
+    "ms_c": ...}."""
     r = GemmTuneResult()
     _check(load_library().btoep_autotune_gemm(op.handle, int(k), 1 if allow_split else 0, int(reps),
                                               _stream(stream), ctypes.byref(r)), "btoep_autotune_gemm", op.handle)
     modes = [0, 1] if (allow_split and op.storage == "f32") else [int(r.split)]
-    return {"k": r.k, "var_n": r.var_n, "var_c": r.var_c, "split": bool(r.split),
+    return {"k": r.k, "nvar_n": r.nvar_n, "nvar_c": r.nvar_c, "var_n": r.var_n, "var_c": r.var_c,
+            "split": bool(r.split),
             "ms_n": {("split" if m else "fp32" if op.storage == "f32" else "bf16"):
                      [round(r.ms_n[m][v], 4) for v in range(r.nvar_n)] for m in modes},
             "ms_c": {("split" if m else "fp32" if op.storage == "f32" else "bf16"):

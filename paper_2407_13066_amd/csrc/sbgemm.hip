@@ -60,17 +60,14 @@ struct Chunk {
 };
 // With several tiles the vector side is staged as ready-made B-operand patterns (16 bytes per
 // column instead of 8, see k_sbgemm_n), so the chunk holds 128 / NT columns.
-template <int NT>
-struct Patterns {
-    static constexpr bool value = NT >= 2;
-};
+static constexpr bool pat_of(int NT, int ch) { return NT >= 2 && ch * NT <= 128; }
 static constexpr int chunk_of(int NT, bool wide) { return NT >= 2 ? 128 / NT : (wide ? 256 : 64); }
 static_assert(Chunk<1, true>::value == chunk_of(1, true) && Chunk<1, false>::value == chunk_of(1, false) &&
                   Chunk<2, true>::value == chunk_of(2, true) && Chunk<4, false>::value == chunk_of(4, false) &&
                   Chunk<8, true>::value == chunk_of(8, true),
               "host and kernel chunk sizes");
 static size_t sbgemm_n_lds(int NT, int ch) {
-    return NT >= 2 ? (size_t)2 * NT * 8 * (ch + 1) * 16 : (size_t)2 * NT * 8 * (ch + 2) * 8;
+    return pat_of(NT, ch) ? (size_t)2 * NT * 8 * (ch + 1) * 16 : (size_t)2 * NT * 8 * (ch + 2) * 8;
 }
 // Launches with fewer (span, frequency) workgroups than this keep 64-column chunks, whose
 // smaller LDS footprint lets more workgroups share a CU.
@@ -132,12 +129,12 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // staged (8 bytes: float complex, or (hi, lo) packed bf16 pairs; row stride kChunk + 2) or,
 // with PAT, both B-operand patterns a lane can need (16 bytes, row stride kChunk + 1): lanes of
 // even result column (real part) take the first 8 bytes, lanes of odd column the second.
-template <int MODE, int NT, int kChunk>
-__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
+template <int MODE, int NT, int kChunk, int OCC>
+__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OCC))) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
                                                            int64_t mh_batch, int nb, cx<float>* __restrict__ part,
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
-    constexpr bool PAT = Patterns<NT>::value;
+    constexpr bool PAT = pat_of(NT, kChunk);
     constexpr bool BF = MODE != kF32;                 // vector side staged as bf16 (hi, lo)
     constexpr int SB = MODE == kBF16 ? 4 : 8;         // bytes of a stored operator entry
     constexpr int LDR = PAT ? kChunk + 1 : kChunk + 2;  // row stride (entries) of a staged chunk
@@ -211,6 +208,28 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
 
+        // BF16 / split modes: the raw operator words of a K step (16-byte groups of 4 columns,
+        // rows s0 and s1), loaded one K step ahead -- across chunk boundaries too -- so their
+        // latency overlaps the current step's matrix-core work.
+        constexpr int WPA = MODE == kSplit ? 2 : 1;  // 16-byte words per row and K step
+        // (row s0 words 0 / 1, row s1 words 0 / 1); the second words are used in split mode only
+        u32x4 c00, c01, c10, c11, n00, n01, n10, n11;
+        auto loadA = [&](int c, int ks, u32x4& w00, u32x4& w01, u32x4& w10, u32x4& w11) {
+            const int64_t col = col0 + c * kChunk + ks * 16 + lg * 4;
+            const u32x4 z = {0u, 0u, 0u, 0u};
+            const bool in = col < col0 + ncol;
+            const u32x4* p0 = reinterpret_cast<const u32x4*>(F0 + col * SB);
+            const u32x4* p1 = reinterpret_cast<const u32x4*>(F1 + col * SB);
+            w00 = in ? p0[0] : z;
+            w10 = in ? p1[0] : z;
+            if constexpr (WPA == 2) {
+                w01 = in ? p0[1] : z;
+                w11 = in ? p1[1] : z;
+            }
+        };
+        if constexpr (BF)
+            if (t0) loadA(0, 0, c00, c01, c10, c11);
+
         cx<float> sv[kPer];
         __syncthreads();
         stage_load(0, sv);
@@ -275,32 +294,31 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
                         }
                     } else {
                         // A operand: 4 complex operator entries of this lane group's columns,
-                        // K order (column q, re / im); kSplit also keeps the remainders
-                        u32x4 a0 = {0u, 0u, 0u, 0u}, a1 = {0u, 0u, 0u, 0u};
-                        u32x4 a0l = {0u, 0u, 0u, 0u}, a1l = {0u, 0u, 0u, 0u};
-                        if (in) {
-                            if constexpr (MODE == kBF16) {
-                                a0 = *(const u32x4*)(F0 + col * 4);
-                                a1 = *(const u32x4*)(F1 + col * 4);
-                            } else {
-                                const u32x4* p0 = (const u32x4*)(F0 + col * 8);
-                                const u32x4* p1 = (const u32x4*)(F1 + col * 8);
-                                const u32x4 w0 = p0[0], w1 = p0[1], x0 = p1[0], x1 = p1[1];
+                        // K order (column q, re / im); kSplit also keeps the remainders.  The
+                        // next step's operator words are requested first.
+                        if (ks + 1 < kChunk / 16)
+                            loadA(c, ks + 1, n00, n01, n10, n11);
+                        else if (c + 1 < nchunk)
+                            loadA(c + 1, 0, n00, n01, n10, n11);
+                        u32x4 a0, a1, a0l = {0u, 0u, 0u, 0u}, a1l = {0u, 0u, 0u, 0u};
+                        if constexpr (MODE == kBF16) {
+                            a0 = c00;
+                            a1 = c10;
+                        } else {
 #pragma unroll
-                                for (int e = 0; e < 2; ++e) {
-                                    uint2 h = split_bf16_hw(w0[2 * e], w0[2 * e + 1]);
-                                    a0[e] = h.x;
-                                    a0l[e] = h.y;
-                                    h = split_bf16_hw(w1[2 * e], w1[2 * e + 1]);
-                                    a0[2 + e] = h.x;
-                                    a0l[2 + e] = h.y;
-                                    h = split_bf16_hw(x0[2 * e], x0[2 * e + 1]);
-                                    a1[e] = h.x;
-                                    a1l[e] = h.y;
-                                    h = split_bf16_hw(x1[2 * e], x1[2 * e + 1]);
-                                    a1[2 + e] = h.x;
-                                    a1l[2 + e] = h.y;
-                                }
+                            for (int e = 0; e < 2; ++e) {
+                                uint2 h = split_bf16_hw(c00[2 * e], c00[2 * e + 1]);
+                                a0[e] = h.x;
+                                a0l[e] = h.y;
+                                h = split_bf16_hw(c01[2 * e], c01[2 * e + 1]);
+                                a0[2 + e] = h.x;
+                                a0l[2 + e] = h.y;
+                                h = split_bf16_hw(c10[2 * e], c10[2 * e + 1]);
+                                a1[e] = h.x;
+                                a1l[e] = h.y;
+                                h = split_bf16_hw(c11[2 * e], c11[2 * e + 1]);
+                                a1[2 + e] = h.x;
+                                a1l[2 + e] = h.y;
                             }
                         }
 #pragma unroll
@@ -328,6 +346,12 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
                                 acc[1][n] = mfma_bf16(a1, bl, acc[1][n]);
                                 if constexpr (MODE == kSplit) acc[1][n] = mfma_bf16(a1l, bh, acc[1][n]);
                             }
+                        }
+                        c00 = n00;
+                        c10 = n10;
+                        if constexpr (WPA == 2) {
+                            c01 = n01;
+                            c11 = n11;
                         }
                     }
                 }
@@ -358,10 +382,13 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4)
 // =========================================================================================
 // C direction.  Grid (ceil(Nm / (32 W)), nfreq); W waves; wave w owns result columns
 // p0 = 32 W blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
-// result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are
-// staged in LDS once (as the A operand pattern's source).
+// result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are staged
+// in LDS once (as the A operand pattern's source), kStageUnroll loads per thread in flight at
+// a time.
 // PF (BF16 and split modes): 1 issues the operator loads of the next K step before the current
-// step's matrix-core work, so one more step of the operator stream is in flight per wave.
+// step's matrix-core work, so one more step of the operator stream is in flight per wave; the
+// first step's loads are then issued before the staging.
+constexpr int kStageUnroll = 8;
 template <int MODE, int NT, int W, int PF>
 __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ dh, int64_t dh_batch, int nb,
@@ -373,162 +400,179 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
     const int f = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    for (int e = threadIdx.x; e < NT * 8 * Ndp; e += 64 * W) {
-        const int r = e / Ndp, s = e % Ndp;
-        float re = 0.f, im = 0.f;
-        if (r < nb && s < Nd) {
-            const cx<float> v = dh[(int64_t)r * dh_batch + (int64_t)f * Nd + s];
-            re = v.re;
-            im = v.im;
-        }
-        uint2 o;
-        if (BF) {
-            split_bf16(re, im, o.x, o.y);
-        } else {
-            o.x = __float_as_uint(re);
-            o.y = __float_as_uint(im);
-        }
-        dsh[e] = o;
-    }
-    __syncthreads();
-
+    const int64_t frow = (int64_t)f * Nd;
     const int pbase = blockIdx.x * (32 * W) + wave * 32;
+    // the two operator columns this lane reads (clamped: always a valid address)
     const int pc[2] = {min(pbase + li, Nm - 1), min(pbase + 16 + li, Nm - 1)};
     const bool tile1 = pbase + 16 < Nm;
-    if (pbase >= Nm) return;
-    f4v acc[2][NT];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
 
-    const int64_t frow = (int64_t)f * Nd;
-    if constexpr (MODE == kF32) {
-        const cx<float>* Fh = (const cx<float>*)Fh_;
-        // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs.  The operator loads
-        // of the next kPre steps are in flight while a step runs.
-        constexpr int kPre = NT >= 4 ? 4 : 1;
-        uint2 ring[kPre][2];
-        auto loadB = [&](int s0, uint2(&dst)[2]) {
-            const int sc = min(s0 + lg, Nd - 1);
-#pragma unroll
-            for (int a = 0; a < 2; ++a) dst[a] = ld_nt8(Fh + (frow + sc) * ldF + pc[a]);
-        };
-#pragma unroll
-        for (int j = 0; j < kPre; ++j)
-            if (4 * j < Nd) loadB(4 * j, ring[j]);
-        for (int sb = 0; sb < Nd; sb += 4 * kPre) {
-#pragma unroll
-            for (int j = 0; j < kPre; ++j) {
-                const int s0 = sb + 4 * j;
-                if (s0 >= Nd) break;
-                const int s = s0 + lg;
-                const bool sv = s < Nd;
-                cx<float> b[2];
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-                    b[a] = sv ? cx<float>{__uint_as_float(ring[j][a].x), __uint_as_float(ring[j][a].y)}
-                              : cx<float>{0.f, 0.f};
-                if (s0 + 4 * kPre < Nd) loadB(s0 + 4 * kPre, ring[j]);
-#pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
-                    const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
-                    const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
-                    const bool imrow = li & 1;
-                    const float a0 = imrow ? dim : dre;   // pairs with Re F
-                    const float a1 = imrow ? -dre : dim;  // pairs with Im F
-#pragma unroll
-                    for (int a = 0; a < 2; ++a) {
-                        acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
-                        acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
-                    }
-                }
-            }
-        }
-    } else {
+    // BF16 / split modes: K step = 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3,
+    // items (re, im).  Raw operator words of one step: a bf16 pair, or the FP32 (re, im)
+    // (split when used).
+    constexpr int WPE = MODE == kSplit ? 2 : 1;
+    struct Raw {
+        uint32_t w[2][4][WPE];
+    };
+    auto load_step = [&](int s0, Raw& raw) {
         const uint32_t* Fh = (const uint32_t*)Fh_;
         const cx<float>* Fh32 = (const cx<float>*)Fh_;
-        // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im).
-        // Raw operator words of one step: a bf16 pair, or the FP32 (re, im) (split when used).
-        constexpr int WPE = MODE == kSplit ? 2 : 1;
-        struct Raw {
-            uint32_t w[2][4][WPE];
-        };
-        auto load_step = [&](int s0, Raw& raw) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int s = s0 + 4 * lg + q;
-                    if constexpr (MODE == kBF16) {
-                        raw.w[a][q][0] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
-                    } else {
-                        const uint2 w = (s < Nd) ? ld_nt8(Fh32 + (frow + s) * ldF + pc[a]) : uint2{0u, 0u};
-                        raw.w[a][q][0] = w.x;
-                        raw.w[a][q][WPE - 1] = w.y;
-                    }
-                }
-        };
-        Raw cur, nxt;
-        if constexpr (PF > 0) load_step(0, cur);
-        for (int s0 = 0; s0 < Nd; s0 += 16) {
-            if constexpr (PF > 0) {
-                if (s0 + 16 < Nd) load_step(s0 + 16, nxt);
-            } else {
-                load_step(s0, cur);
-            }
-            u32x4 b[2], bl[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if constexpr (MODE == kBF16) {
-                        b[a][q] = cur.w[a][q][0];
-                    } else {
-                        const uint2 h = split_bf16_hw(cur.w[a][q][0], cur.w[a][q][WPE - 1]);
-                        b[a][q] = h.x;
-                        bl[a][q] = h.y;
-                    }
-                }
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const int r = n * 8 + (li >> 1);
-                const bool imrow = li & 1;
-                u32x4 ah, al;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int s = s0 + 4 * lg + q;  // < Ndp; zero-filled past Nd
-                    const uint2 dv = dsh[r * Ndp + s];
-                    // K items (re F, im F) pair with (Re d, Im d) for the real row, (Im d, -Re d) for the imaginary row
-                    ah[q] = imrow ? bf_im_negre(dv.x) : dv.x;
-                    al[q] = imrow ? bf_im_negre(dv.y) : dv.y;
-                }
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    acc[a][n] = mfma_bf16(ah, b[a], acc[a][n]);
-                    acc[a][n] = mfma_bf16(al, b[a], acc[a][n]);
-                    if constexpr (MODE == kSplit) acc[a][n] = mfma_bf16(ah, bl[a], acc[a][n]);
+            for (int k = 0; k < 4; ++k) {
+                const int s = s0 + 4 * lg + k;
+                if constexpr (MODE == kBF16) {
+                    raw.w[a][k][0] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
+                } else {
+                    const uint2 w = (s < Nd) ? ld_nt8(Fh32 + (frow + s) * ldF + pc[a]) : uint2{0u, 0u};
+                    raw.w[a][k][0] = w.x;
+                    raw.w[a][k][WPE - 1] = w.y;
                 }
             }
-            if constexpr (PF > 0) cur = nxt;
+    };
+    Raw cur, nxt;
+    if constexpr (BF && PF > 0) load_step(0, cur);
+
+    // staging: kStageUnroll loads per thread issued together, then split and stored
+    const int total = NT * 8 * Ndp;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kStageUnroll * 64 * W) {
+        cx<float> v[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int e = e0 + u * 64 * W;
+            const int r = e / Ndp, s = e % Ndp;
+            v[u] = cx<float>{0.f, 0.f};
+            if (e < total && r < nb && s < Nd) v[u] = dh[(int64_t)r * dh_batch + (int64_t)f * Nd + s];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int e = e0 + u * 64 * W;
+            if (e < total) {
+                uint2 o;
+                if (BF) {
+                    split_bf16(v[u].re, v[u].im, o.x, o.y);
+                } else {
+                    o.x = __float_as_uint(v[u].re);
+                    o.y = __float_as_uint(v[u].im);
+                }
+                dsh[e] = o;
+            }
         }
     }
-    // C[4 lg + v][li]: result row 4 lg + v -> rhs n*8 + 2 lg + v/2, part v&1; column p = tile + li
+    __syncthreads();
+    if (pbase >= Nm) return;
+
+    {
+        f4v acc[2][NT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int p = pbase + 16 * a + li;
-        if (p >= Nm || (a == 1 && !tile1)) continue;
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
+            for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
+
+        if constexpr (MODE == kF32) {
+            const cx<float>* Fh = (const cx<float>*)Fh_;
+            // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs.  The operator
+            // loads of the next kPre steps are in flight while a step runs.
+            constexpr int kPre = NT >= 4 ? 4 : 1;
+            uint2 ring[kPre][2];
+            auto loadB = [&](int s0, uint2(&dst)[2]) {
+                const int sc = min(s0 + lg, Nd - 1);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = n * 8 + 2 * lg + h;
-                if (r < nb) {
-                    // not read again by this launch: non-temporal store
-                    typedef float f2v __attribute__((ext_vector_type(2)));
-                    const f2v w = {acc[a][n][2 * h], acc[a][n][2 * h + 1]};
-                    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(mo + (int64_t)r * mo_batch + (int64_t)f * ldv + p));
+                for (int a = 0; a < 2; ++a) dst[a] = ld_nt8(Fh + (frow + sc) * ldF + pc[a]);
+            };
+#pragma unroll
+            for (int j = 0; j < kPre; ++j)
+                if (4 * j < Nd) loadB(4 * j, ring[j]);
+            for (int sb = 0; sb < Nd; sb += 4 * kPre) {
+#pragma unroll
+                for (int j = 0; j < kPre; ++j) {
+                    const int s0 = sb + 4 * j;
+                    if (s0 >= Nd) break;
+                    const int s = s0 + lg;
+                    const bool sv = s < Nd;
+                    cx<float> b[2];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+                        b[a] = sv ? cx<float>{__uint_as_float(ring[j][a].x), __uint_as_float(ring[j][a].y)}
+                                  : cx<float>{0.f, 0.f};
+                    if (s0 + 4 * kPre < Nd) loadB(s0 + 4 * kPre, ring[j]);
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) {
+                        // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
+                        const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
+                        const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
+                        const bool imrow = li & 1;
+                        const float a0 = imrow ? dim : dre;   // pairs with Re F
+                        const float a1 = imrow ? -dre : dim;  // pairs with Im F
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
+                            acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
+                        }
+                    }
+                }
+            }
+        } else {
+            for (int s0 = 0; s0 < Nd; s0 += 16) {
+                if constexpr (PF > 0) {
+                    if (s0 + 16 < Nd) load_step(s0 + 16, nxt);
+                } else {
+                    load_step(s0, cur);
+                }
+                u32x4 b[2], bl[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if constexpr (MODE == kBF16) {
+                            b[a][k] = cur.w[a][k][0];
+                        } else {
+                            const uint2 h = split_bf16_hw(cur.w[a][k][0], cur.w[a][k][WPE - 1]);
+                            b[a][k] = h.x;
+                            bl[a][k] = h.y;
+                        }
+                    }
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const int r = n * 8 + (li >> 1);
+                    const bool imrow = li & 1;
+                    u32x4 ah, al;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int s = s0 + 4 * lg + k;  // < Ndp; zero-filled past Nd
+                        const uint2 dv = dsh[r * Ndp + s];
+                        // K items (re F, im F) pair with (Re d, Im d) for the real row, (Im d, -Re d)
+                        // for the imaginary row
+                        ah[k] = imrow ? bf_im_negre(dv.x) : dv.x;
+                        al[k] = imrow ? bf_im_negre(dv.y) : dv.y;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        acc[a][n] = mfma_bf16(ah, b[a], acc[a][n]);
+                        acc[a][n] = mfma_bf16(al, b[a], acc[a][n]);
+                        if constexpr (MODE == kSplit) acc[a][n] = mfma_bf16(ah, bl[a], acc[a][n]);
+                    }
+                }
+                if constexpr (PF > 0) cur = nxt;
+            }
+        }
+        // C[4 lg + v][li]: result row 4 lg + v -> rhs n*8 + 2 lg + v/2, part v&1; column p = tile + li
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int p = pbase + 16 * a + li;
+            if (p >= Nm || (a == 1 && !tile1)) continue;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = n * 8 + 2 * lg + h;
+                    if (r < nb) {
+                        // not read again by this launch: non-temporal store
+                        typedef float f2v __attribute__((ext_vector_type(2)));
+                        const f2v w = {acc[a][n][2 * h], acc[a][n][2 * h + 1]};
+                        __builtin_nontemporal_store(
+                            w, reinterpret_cast<f2v*>(mo + (int64_t)r * mo_batch + (int64_t)f * ldv + p));
+                    }
                 }
             }
         }
@@ -546,9 +590,11 @@ static int nt_of(int nb) { return nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 
 // Variants of the N kernel: 0 the default (right-hand sides in groups of at most kGemmNMax,
 // wide chunks on launches of >= kWideGrid workgroups), 1 groups of up to 64 (one pass over
 // the operator for up to 64 right-hand sides, eight-tile kernel), 2 / 3 narrow / wide chunks
-// on every launch.
-int sbgemm_n_variants() { return 4; }
-int sbgemm_n_group(int var) { return var == 1 ? kMaxBatch : kGemmNMax; }
+// on every launch, 4 as 1 with the register budget of two waves per SIMD instead of four
+// (four or more tiles, whose accumulators and operator prefetch spill at four; below that it
+// equals 1).
+int sbgemm_n_variants() { return 5; }
+int sbgemm_n_group(int var) { return (var == 1 || var == 4) ? kMaxBatch : kGemmNMax; }
 
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
@@ -557,19 +603,23 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     const int CS = n_span_cols(st, Nm, nfreq);  // the single-vector kernel's spans (multiples of 256 columns)
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
-    const bool wide = var == 2 ? false : (var == 3 ? true : (int64_t)nspan * nfreq >= kWideGrid);
+    const bool occ2 = var == 4 && NT >= 4;
+    const bool wide = occ2 || (var == 2 ? false : (var == 3 ? true : (int64_t)nspan * nfreq >= kWideGrid));
     const size_t lds = sbgemm_n_lds(NT, chunk_of(NT, wide));
     dim3 grid(nspan, nfreq), block(kGemmThreads);
     const cx<float>* m = (const cx<float>*)mh;
     cx<float>* p = (cx<float>*)part;
-#define BT_GN(BFV, NTV)                                                                                    \
-    do {                                                                                                   \
-        if (wide)                                                                                          \
-            k_sbgemm_n<BFV, NTV, Chunk<NTV, true>::value><<<grid, block, lds, s>>>(                        \
-                Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, part_batch);                   \
-        else                                                                                               \
-            k_sbgemm_n<BFV, NTV, Chunk<NTV, false>::value><<<grid, block, lds, s>>>(                       \
-                Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, nfreq, part_batch);                   \
+#define BT_GN_K(BFV, NTV, CHV, OCCV)                                                                       \
+    k_sbgemm_n<BFV, NTV, CHV, OCCV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, m, ldv, mh_batch, nb, p, CS, nspan, \
+                                                           nfreq, part_batch)
+#define BT_GN(BFV, NTV)                                                            \
+    do {                                                                           \
+        if (occ2 && NTV >= 4)                                                      \
+            BT_GN_K(BFV, NTV, (Chunk<NTV, true>::value), (NTV >= 4 ? 2 : 4));      \
+        else if (wide)                                                             \
+            BT_GN_K(BFV, NTV, (Chunk<NTV, true>::value), 4);                       \
+        else                                                                       \
+            BT_GN_K(BFV, NTV, (Chunk<NTV, false>::value), 4);                      \
     } while (0)
     const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
 #define BT_GN_MODE(NTV)                     \
@@ -586,6 +636,7 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     }
 #undef BT_GN_MODE
 #undef BT_GN
+#undef BT_GN_K
     return hipGetLastError();
 }
 
@@ -611,16 +662,18 @@ hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     dim3 grid((unsigned)((Nm + 32 * W - 1) / (32 * W)), nfreq), block(64 * W);
     const cx<float>* d = (const cx<float>*)dh;
     cx<float>* o = (cx<float>*)mo;
-#define BT_GC(BFV, NTV)                                                                                          \
-    do {                                                                                                         \
-        if (W == 4 && PF == 0)                                                                                   \
-            k_sbgemm_c<BFV, NTV, 4, 0><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
-        else if (W == 4)                                                                                         \
-            k_sbgemm_c<BFV, NTV, 4, 1><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
-        else if (PF == 0)                                                                                        \
-            k_sbgemm_c<BFV, NTV, 8, 0><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
-        else                                                                                                     \
-            k_sbgemm_c<BFV, NTV, 8, 1><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch); \
+#define BT_GC_K(BFV, NTV, WV, PFV) \
+    k_sbgemm_c<BFV, NTV, WV, PFV><<<grid, block, lds, s>>>(Fh, ldF, Nd, Nm, d, dh_batch, nb, o, ldv, mo_batch)
+#define BT_GC(BFV, NTV)                      \
+    do {                                     \
+        if (W == 4 && PF == 0)               \
+            BT_GC_K(BFV, NTV, 4, 0);         \
+        else if (W == 4)                     \
+            BT_GC_K(BFV, NTV, 4, 1);         \
+        else if (PF == 0)                    \
+            BT_GC_K(BFV, NTV, 8, 0);         \
+        else                                 \
+            BT_GC_K(BFV, NTV, 8, 1);         \
     } while (0)
     const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
 #define BT_GC_MODE(NTV)                     \
@@ -637,6 +690,7 @@ hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     }
 #undef BT_GC_MODE
 #undef BT_GC
+#undef BT_GC_K
     return hipGetLastError();
 }
 

@@ -300,6 +300,10 @@ def test_extreme_sensor_and_parameter_counts(bt, shape, storage, k):
     assert e.value.status == 4
 
 
+# matrix-core kernel variants the library offers (forward, adjoint)
+N_GEMM_N_VARIANTS, N_GEMM_C_VARIANTS = 5, 5
+
+
 @pytest.mark.parametrize("storage", ["f32", "f32split", "bf16"])
 def test_every_matrix_core_variant_and_gemm_autotune(bt, storage):
     """Every forward and adjoint matrix-core kernel variant, in every right-hand-side bucket
@@ -317,7 +321,7 @@ def test_every_matrix_core_variant_and_gemm_autotune(bt, storage):
         Md, Dd = to_dev(M, torch.float32), to_dev(D, torch.float32)
         FM_ref = oracle.apply_F(blocks, M.astype(np.float64))
         FTD_ref = oracle.apply_FT(blocks, D.astype(np.float64))
-        combos = [(v, 0) for v in range(4)] + [(0, v) for v in range(1, 5)]
+        combos = [(v, 0) for v in range(N_GEMM_N_VARIANTS)] + [(0, v) for v in range(1, N_GEMM_C_VARIANTS)]
         for var_n, var_c in combos:
             bt.btoep_set_gemm_variants(op, k, var_n, var_c)
             FM = bt.btoep_apply_F(op, Md).double().cpu().numpy()
@@ -326,12 +330,15 @@ def test_every_matrix_core_variant_and_gemm_autotune(bt, storage):
                 assert oracle.rel_l2(FM[r], FM_ref[r]) <= tol, ("F", k, var_n, r)
                 assert oracle.rel_l2(FTD[r], FTD_ref[r]) <= tol, ("FT", k, var_c, r)
         tune = bt.btoep_autotune_gemm(op, k, allow_split=(storage == "f32split"), reps=2)
-        assert 0 <= tune["var_n"] < 4 and 0 <= tune["var_c"] < 5
+        assert tune["nvar_n"] == N_GEMM_N_VARIANTS and tune["nvar_c"] == N_GEMM_C_VARIANTS
+        assert 0 <= tune["var_n"] < N_GEMM_N_VARIANTS and 0 <= tune["var_c"] < N_GEMM_C_VARIANTS
         HM = bt.btoep_apply_H(op, Md, 1.5, 0.75).double().cpu().numpy()
         HM_ref = oracle.apply_H(blocks, M[:3].astype(np.float64), 1.5, 0.75)
         for r in range(3):
             assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol, ("H after autotune", k, tune)
     with pytest.raises(bt.BtoepError):
-        bt.btoep_set_gemm_variants(op, 9, 4, 0)   # no such forward variant
+        bt.btoep_set_gemm_variants(op, 9, N_GEMM_N_VARIANTS, 0)   # no such forward variant
+    with pytest.raises(bt.BtoepError):
+        bt.btoep_set_gemm_variants(op, 9, 0, N_GEMM_C_VARIANTS)   # no such adjoint variant
     with pytest.raises(bt.BtoepError):
         bt.btoep_set_gemm_variants(op, 1, 0, 0)   # one right-hand side has no matrix-core product
