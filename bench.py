@@ -216,8 +216,6 @@ def serving_benchmark(bt, n_req, rates, seed=13066, n_cap=200, check=True):
     log("serving operators: " + ", ".join("%s %s %.2f GB (+ %.2f GB FP64)" % (
         n, shapes[i], ops[n].info["fhat_bytes"] / 1e9, ops_hi[n].info["fhat_bytes"] / 1e9)
         for i, n in enumerate("ABC")))
-    for op in list(ops.values()) + list(ops_hi.values()):
-        bt.btoep_autotune(op, reps=2)
     rng = np.random.default_rng(seed)
     gen = torch.Generator(device="cuda").manual_seed(seed)
     kinds = ("F", "FT", "H", "CG")
@@ -253,6 +251,11 @@ def serving_benchmark(bt, n_req, rates, seed=13066, n_cap=200, check=True):
     # graphs for every batch shape the server can form, captured before any timing
     ex_graph = GpuExecutor(ops, n_streams=2, max_batch=32, use_graphs=True, ops_hi=ops_hi)
     ex_eager = GpuExecutor(ops, n_streams=2, max_batch=32, use_graphs=False, ops_hi=ops_hi)
+    tuned = ex_graph.autotune(reps=2)   # the operators are shared: this tunes both executors
+    log("serving autotune (matrix cores, per bucket: forward / adjoint variant, split): " + "; ".join(
+        "%s %s" % (name, " ".join("k%d %d/%d%s" % (k, t["var_n"], t["var_c"], "s" if t["split"] else "")
+                                  for k, t in res["gemm"].items()))
+        for (name, level), res in tuned.items() if "gemm" in res))
     t0 = time.perf_counter()
     pipes = [(n, p, nz, pr) for n in "ABC" for p, nz, pr in (("F", 0.0, 0.0), ("FT", 0.0, 0.0), ("H", noise, prior))]
     ex_graph.prepare_graphs(pipes, range(1, 33))
@@ -320,6 +323,9 @@ def serving_benchmark(bt, n_req, rates, seed=13066, n_cap=200, check=True):
     capacity = (i90 - i10) / (t_done[i90] - t_done[i10])
     log("serving capacity (saturating run of %d requests, 10-90%% window): %.1f requests/s" % (n_cap, capacity))
     out = {"operators": {n: list(shapes[i]) for i, n in enumerate("ABC")}, "storage": "c64 (+ c128 for CG refinement)",
+           "gemm_autotune": {name: {"k%d" % k: {"var_n": t["var_n"], "var_c": t["var_c"], "split_bf16": t["split"]}
+                                    for k, t in res["gemm"].items()}
+                             for (name, level), res in tuned.items() if "gemm" in res},
            "graphs": {"count": len(ex_graph.graphs), "capture_s": round(capture_s, 2), "per_apply_ms": launch_cost},
            "capacity_requests_per_s": round(capacity, 2),
            "capacity_run": dict(cap, window="10th-90th percentile completions"), "rates": {}}

@@ -346,7 +346,8 @@ hipError_t prod_c(btoep_op op, int nb, const void* dh, int64_t dh_b, void* vh, i
         const bool f64 = op->stor == Stor::C128;
         const size_t cb = 2 * vbytes(op);  // bytes of a vector-side complex value
         int g = f64 ? std::min(nb, kGemmNMax) : nb;
-        while (g > 1 && (f64 ? sbgemm_c64_lds(g, Nd) : sbgemm_c_lds(g, Nd)) > 64 * 1024) g = (g + 1) / 2;
+        const bool bf = op->stor == Stor::BF16 || op->gsplit[gemm_bucket(nb)];
+        while (g > 1 && (f64 ? sbgemm_c64_lds(g, Nd) : sbgemm_c_lds(g, Nd, bf)) > 64 * 1024) g = (g + 1) / 2;
         for (int r0 = 0; r0 < nb; r0 += g) {
             const int n = std::min(g, nb - r0);
             const void* d = (const char*)dh + (size_t)r0 * dh_b * cb;

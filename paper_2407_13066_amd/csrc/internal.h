@@ -117,8 +117,9 @@ hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
 
 // ---- launchers (sbgemm.hip): k >= 2 right-hand sides on the matrix cores ----------------
 // Same operands and outputs as the single-vector launchers above, for nb right-hand sides in
-// one launch (FP32 or BF16 storage only).  sbgemm_c needs sbgemm_c_lds(nb, Nd) <= 64 KB.
-size_t sbgemm_c_lds(int nb, int Nd);
+// one launch (FP32 or BF16 storage only).  sbgemm_c needs sbgemm_c_lds(nb, Nd, bf) <= 64 KB
+// (bf: BF16 storage or the split mode, whose staging is phased and fits any Nd).
+size_t sbgemm_c_lds(int nb, int Nd, bool bf);
 // The N launcher takes at most kGemmNMax right-hand sides (an 8-tile N kernel measured slower
 // than two 4-tile launches); callers group larger batches.
 constexpr int kGemmNMax = 32;

@@ -61,13 +61,17 @@ struct Chunk {
 // With several tiles the vector side is staged as ready-made B-operand patterns (16 bytes per
 // column instead of 8, see k_sbgemm_n), so the chunk holds 128 / NT columns.
 static constexpr bool pat_of(int NT, int ch) { return NT >= 2 && ch * NT <= 128; }
+// Row stride (bytes) of the grouped pattern blocks of BF16 / split staging: 64 bytes per group
+// of 4 columns plus one spare group.
+static constexpr int gp_row_bytes(int ch) { return 16 * ch + 64; }
 static constexpr int chunk_of(int NT, bool wide) { return NT >= 2 ? 128 / NT : (wide ? 256 : 64); }
 static_assert(Chunk<1, true>::value == chunk_of(1, true) && Chunk<1, false>::value == chunk_of(1, false) &&
                   Chunk<2, true>::value == chunk_of(2, true) && Chunk<4, false>::value == chunk_of(4, false) &&
                   Chunk<8, true>::value == chunk_of(8, true),
               "host and kernel chunk sizes");
-static size_t sbgemm_n_lds(int NT, int ch) {
-    return pat_of(NT, ch) ? (size_t)2 * NT * 8 * (ch + 1) * 16 : (size_t)2 * NT * 8 * (ch + 2) * 8;
+static size_t sbgemm_n_lds(int NT, int ch, bool bf) {
+    if (pat_of(NT, ch)) return bf ? (size_t)2 * NT * 8 * gp_row_bytes(ch) : (size_t)2 * NT * 8 * (ch + 1) * 16;
+    return (size_t)2 * NT * 8 * (ch + 2) * 8;
 }
 // Launches with fewer (span, frequency) workgroups than this keep 64-column chunks, whose
 // smaller LDS footprint lets more workgroups share a CU.
@@ -99,16 +103,9 @@ __device__ __forceinline__ f4v mfma_bf16(u32x4 a, u32x4 b, f4v c) {
                                                    0, 0);
 }
 
-// (re, im) of a float complex as bf16 high parts and bf16 remainders, packed re | im << 16.
-__device__ __forceinline__ void split_bf16(float re, float im, uint32_t& hi, uint32_t& lo) {
-    const uint32_t rh = f32_to_bf16_rne(re), ih = f32_to_bf16_rne(im);
-    const float rr = re - __uint_as_float(rh << 16), ir = im - __uint_as_float(ih << 16);
-    hi = rh | (ih << 16);
-    lo = f32_to_bf16_rne(rr) | (f32_to_bf16_rne(ir) << 16);
-}
-// (re, im) of an FP32 operator entry (raw bits) as packed bf16 high parts and remainders, with
-// the packed round-to-nearest-even conversion of gfx950; the remainder re - hi is exact in FP32.
-// Returns (hi, lo).
+// (re, im) of an FP32 complex value (raw bits) as packed bf16 high parts and remainders
+// (re | im << 16), with the packed round-to-nearest-even conversion of gfx950; the remainder
+// re - hi is exact in FP32.  Returns (hi, lo).
 __device__ __forceinline__ uint2 split_bf16_hw(uint32_t re_bits, uint32_t im_bits) {
     const f2v_t x = {__uint_as_float(re_bits), __uint_as_float(im_bits)};
     const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf2v));
@@ -127,8 +124,12 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // of 128 rows; NT tiles of 16 real result columns (8 right-hand sides each).
 // LDS: two chunk buffers of nb x kChunk vector entries.  An entry is the column's value as
 // staged (8 bytes: float complex, or (hi, lo) packed bf16 pairs; row stride kChunk + 2) or,
-// with PAT, both B-operand patterns a lane can need (16 bytes, row stride kChunk + 1): lanes of
-// even result column (real part) take the first 8 bytes, lanes of odd column the second.
+// with PAT, both B-operand patterns a lane can need: FP32 mode 16 bytes per column (row stride
+// kChunk + 1), lanes of even result column (real part) taking the first 8 bytes, lanes of odd
+// column the second; BF16 and split modes (GP) one 64-byte block per group of 4 columns,
+// [real-column hi x4 | real-column lo x4 | imaginary-column hi x4 | imaginary-column lo x4],
+// so that a lane's B operands are two aligned 16-byte LDS reads (row stride 64 kChunk / 4 +
+// 64 bytes, which keeps a wave's reads free of bank conflicts).
 template <int MODE, int NT, int kChunk, int OCC>
 __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OCC))) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
@@ -136,15 +137,18 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
     constexpr bool PAT = pat_of(NT, kChunk);
     constexpr bool BF = MODE != kF32;                 // vector side staged as bf16 (hi, lo)
+    constexpr bool GP = PAT && BF;                    // grouped 64-byte pattern blocks
     constexpr int SB = MODE == kBF16 ? 4 : 8;         // bytes of a stored operator entry
     constexpr int LDR = PAT ? kChunk + 1 : kChunk + 2;  // row stride (entries) of a staged chunk
+    constexpr int GS = gp_row_bytes(kChunk);          // row stride (bytes) of a GP chunk
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint2* buf = reinterpret_cast<uint2*>(smem_raw);   // [2][NT*8][LDR] 8-byte entries
     uint4* buf4 = reinterpret_cast<uint4*>(smem_raw);  // [2][NT*8][LDR] 16-byte entries (PAT)
     const int span = blockIdx.x, f = blockIdx.y;
     const int col0 = span * CS;
     const int ncol = min(CS, Nm - col0);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar branches
     const int li = lane & 15, lg = lane >> 4;
     const int nchunk = (ncol + kChunk - 1) / kChunk;
     const int rows_per_buf = NT * 8;
@@ -165,6 +169,25 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
         }
     };
     auto stage_store = [&](int which, const cx<float>* v) {
+        if constexpr (GP) {
+            // entry (r, q) -> word q % 4 of the four 16-byte planes of block (r, q / 4); the loads
+            // above stay lane-contiguous (coalesced), the scatter happens in the LDS writes
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int e = threadIdx.x + i * kGemmThreads;
+                const int r = e / kChunk, q = e % kChunk;
+                const uint2 h = split_bf16_hw(__float_as_uint(v[i].re), __float_as_uint(v[i].im));
+                uint32_t* dst = reinterpret_cast<uint32_t*>(smem_raw + (size_t)which * rows_per_buf * GS + r * GS +
+                                                            (q >> 2) * 64 + (q & 3) * 4);
+                // (Re m, -Im m) pairs with (Re F, Im F) for a real-part column, (Im m, Re m) for
+                // an imaginary-part column
+                dst[0] = bf_re_negim(h.x);
+                dst[4] = bf_re_negim(h.y);
+                dst[8] = bf_im_re(h.x);
+                dst[12] = bf_im_re(h.y);
+            }
+            return;
+        }
         uint2* dst = buf + (size_t)which * rows_per_buf * LDR;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
@@ -176,9 +199,8 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                 // imaginary-part column: (Re m, -Im m), (Im m, Re m)
                 uint4 out;
                 if (BF) {
-                    uint32_t hi, lo;
-                    split_bf16(re, im, hi, lo);
-                    out = uint4{bf_re_negim(hi), bf_re_negim(lo), bf_im_re(hi), bf_im_re(lo)};
+                    const uint2 h = split_bf16_hw(__float_as_uint(re), __float_as_uint(im));
+                    out = uint4{bf_re_negim(h.x), bf_re_negim(h.y), bf_im_re(h.x), bf_im_re(h.y)};
                 } else {
                     out = uint4{__float_as_uint(re), __float_as_uint(-im), __float_as_uint(im), __float_as_uint(re)};
                 }
@@ -186,7 +208,7 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
             } else {
                 uint2 out;
                 if (BF) {
-                    split_bf16(re, im, out.x, out.y);
+                    out = split_bf16_hw(__float_as_uint(re), __float_as_uint(im));
                 } else {
                     out.x = __float_as_uint(re);
                     out.y = __float_as_uint(im);
@@ -198,7 +220,7 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
 
     for (int rg = 0; rg < Nd; rg += 128) {
         const int rt0 = rg + wave * 32;  // first row of this wave's two 16-row tiles
-        const bool t0 = rt0 < Nd, t1 = rt0 + 16 < Nd;
+        const bool t0 = rt0 < Nd;
         const int s0 = min(rt0 + li, Nd - 1), s1 = min(rt0 + 16 + li, Nd - 1);
         const char* F0 = (const char*)Fh_ + ((int64_t)f * Nd + s0) * ldF * SB;
         const char* F1 = (const char*)Fh_ + ((int64_t)f * Nd + s1) * ldF * SB;
@@ -284,12 +306,12 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                                     b0 = imcol ? mim : mre;
                                     b1 = imcol ? mre : -mim;
                                 }
+                                // the second tile is computed even past Nd (rows clamped to a
+                                // valid one, results not stored): no divergent accumulators
                                 acc[0][n] = mfma_f32(a0[2 * q], b0, acc[0][n]);
                                 acc[0][n] = mfma_f32(a0[2 * q + 1], b1, acc[0][n]);
-                                if (t1) {
-                                    acc[1][n] = mfma_f32(a1[2 * q], b0, acc[1][n]);
-                                    acc[1][n] = mfma_f32(a1[2 * q + 1], b1, acc[1][n]);
-                                }
+                                acc[1][n] = mfma_f32(a1[2 * q], b0, acc[1][n]);
+                                acc[1][n] = mfma_f32(a1[2 * q + 1], b1, acc[1][n]);
                             }
                         }
                     } else {
@@ -326,13 +348,14 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                             const int r = n * 8 + (li >> 1);
                             const bool imcol = li & 1;
                             u32x4 bh, bl;
+                            if constexpr (GP) {
+                                const u32x4* pb = reinterpret_cast<const u32x4*>(
+                                    smem_raw + (size_t)(c & 1) * rows_per_buf * GS + r * GS + (q0 >> 2) * 64 + imcol * 32);
+                                bh = pb[0];
+                                bl = pb[1];
+                            } else {
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                if constexpr (PAT) {
-                                    const uint2 pv = reinterpret_cast<const uint2*>(B4 + r * LDR + q0 + q)[imcol];
-                                    bh[q] = pv.x;
-                                    bl[q] = pv.y;
-                                } else {
+                                for (int q = 0; q < 4; ++q) {
                                     const uint2 mv = B[r * LDR + q0 + q];
                                     bh[q] = imcol ? bf_im_re(mv.x) : bf_re_negim(mv.x);
                                     bl[q] = imcol ? bf_im_re(mv.y) : bf_re_negim(mv.y);
@@ -341,11 +364,9 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                             acc[0][n] = mfma_bf16(a0, bh, acc[0][n]);
                             acc[0][n] = mfma_bf16(a0, bl, acc[0][n]);
                             if constexpr (MODE == kSplit) acc[0][n] = mfma_bf16(a0l, bh, acc[0][n]);
-                            if (t1) {
-                                acc[1][n] = mfma_bf16(a1, bh, acc[1][n]);
-                                acc[1][n] = mfma_bf16(a1, bl, acc[1][n]);
-                                if constexpr (MODE == kSplit) acc[1][n] = mfma_bf16(a1l, bh, acc[1][n]);
-                            }
+                            acc[1][n] = mfma_bf16(a1, bh, acc[1][n]);
+                            acc[1][n] = mfma_bf16(a1, bl, acc[1][n]);
+                            if constexpr (MODE == kSplit) acc[1][n] = mfma_bf16(a1l, bh, acc[1][n]);
                         }
                         c00 = n00;
                         c10 = n10;
@@ -383,137 +404,183 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
 // C direction.  Grid (ceil(Nm / (32 W)), nfreq); W waves; wave w owns result columns
 // p0 = 32 W blockIdx.x + 32 w + [0, 32) as two 16-column tiles; NT row tiles of 16 real
 // result rows (8 right-hand sides).  The data spectra dh[r][f][s] of this frequency are staged
-// in LDS once (as the A operand pattern's source), kStageUnroll loads per thread in flight at
-// a time.
+// in LDS (as the A operand's source), kStageUnroll loads per thread in flight at a time.
+//   FP32 mode: all Nd sensors at once, one 8-byte entry per (r, s); a lane forms the
+//     imaginary-row pattern itself.
+//   BF16 / split modes (GP): both A-operand patterns ready-made, one 64-byte block per
+//     (r, group of 4 sensors) = [real-row hi x4 | real-row lo x4 | imaginary-row hi x4 |
+//     imaginary-row lo x4], so a lane's A operands are two aligned 16-byte LDS reads and the
+//     inner loop has no pattern arithmetic; staged c_phase_sensors(NT) sensors at a time (the
+//     LDS bound), with a barrier between phases.  Row stride 16 KH + 64 bytes keeps a wave's
+//     reads free of bank conflicts.
 // PF (BF16 and split modes): 1 issues the operator loads of the next K step before the current
 // step's matrix-core work, so one more step of the operator stream is in flight per wave; the
 // first step's loads are then issued before the staging.
 constexpr int kStageUnroll = 8;
+static constexpr int c_phase_sensors(int NT) {
+    // largest multiple of 16 with NT * 8 * (16 KH + 64) <= 64 KB
+    return ((65536 / (NT * 8) - 64) / 16) / 16 * 16;
+}
+static constexpr int c_gp_row_bytes(int NT) { return 16 * c_phase_sensors(NT) + 64; }
+
 template <int MODE, int NT, int W, int PF>
 __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ dh, int64_t dh_batch, int nb,
                                                            cx<float>* __restrict__ mo, int64_t ldv, int64_t mo_batch) {
-    constexpr bool BF = MODE != kF32;  // data spectra staged as bf16 (hi, lo)
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    uint2* dsh = reinterpret_cast<uint2*>(smem_raw);  // [NT*8][Ndp]: float complex or (hi, lo) bf16 pairs
     const int Ndp = (Nd + 15) & ~15;
     const int f = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar branches
     const int li = lane & 15, lg = lane >> 4;
     const int64_t frow = (int64_t)f * Nd;
     const int pbase = blockIdx.x * (32 * W) + wave * 32;
     // the two operator columns this lane reads (clamped: always a valid address)
     const int pc[2] = {min(pbase + li, Nm - 1), min(pbase + 16 + li, Nm - 1)};
     const bool tile1 = pbase + 16 < Nm;
+    const bool live = pbase < Nm;
+    f4v acc[2][NT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
 
-    // BF16 / split modes: K step = 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3,
-    // items (re, im).  Raw operator words of one step: a bf16 pair, or the FP32 (re, im)
-    // (split when used).
-    constexpr int WPE = MODE == kSplit ? 2 : 1;
-    struct Raw {
-        uint32_t w[2][4][WPE];
-    };
-    auto load_step = [&](int s0, Raw& raw) {
-        const uint32_t* Fh = (const uint32_t*)Fh_;
-        const cx<float>* Fh32 = (const cx<float>*)Fh_;
+    if constexpr (MODE == kF32) {
+        uint2* dsh = reinterpret_cast<uint2*>(smem_raw);  // [NT*8][Ndp] float complex
+        const int total = NT * 8 * Ndp;
+        for (int e0 = threadIdx.x; e0 < total; e0 += kStageUnroll * 64 * W) {
+            cx<float> v[kStageUnroll];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int s = s0 + 4 * lg + k;
-                if constexpr (MODE == kBF16) {
-                    raw.w[a][k][0] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
-                } else {
-                    const uint2 w = (s < Nd) ? ld_nt8(Fh32 + (frow + s) * ldF + pc[a]) : uint2{0u, 0u};
-                    raw.w[a][k][0] = w.x;
-                    raw.w[a][k][WPE - 1] = w.y;
-                }
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int e = e0 + u * 64 * W;
+                const int r = e / Ndp, s = e % Ndp;
+                v[u] = cx<float>{0.f, 0.f};
+                if (e < total && r < nb && s < Nd) v[u] = dh[(int64_t)r * dh_batch + (int64_t)f * Nd + s];
             }
-    };
-    Raw cur, nxt;
-    if constexpr (BF && PF > 0) load_step(0, cur);
-
-    // staging: kStageUnroll loads per thread issued together, then split and stored
-    const int total = NT * 8 * Ndp;
-    for (int e0 = threadIdx.x; e0 < total; e0 += kStageUnroll * 64 * W) {
-        cx<float> v[kStageUnroll];
 #pragma unroll
-        for (int u = 0; u < kStageUnroll; ++u) {
-            const int e = e0 + u * 64 * W;
-            const int r = e / Ndp, s = e % Ndp;
-            v[u] = cx<float>{0.f, 0.f};
-            if (e < total && r < nb && s < Nd) v[u] = dh[(int64_t)r * dh_batch + (int64_t)f * Nd + s];
-        }
-#pragma unroll
-        for (int u = 0; u < kStageUnroll; ++u) {
-            const int e = e0 + u * 64 * W;
-            if (e < total) {
-                uint2 o;
-                if (BF) {
-                    split_bf16(v[u].re, v[u].im, o.x, o.y);
-                } else {
-                    o.x = __float_as_uint(v[u].re);
-                    o.y = __float_as_uint(v[u].im);
-                }
-                dsh[e] = o;
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int e = e0 + u * 64 * W;
+                if (e < total) dsh[e] = uint2{__float_as_uint(v[u].re), __float_as_uint(v[u].im)};
             }
         }
-    }
-    __syncthreads();
-    if (pbase >= Nm) return;
-
-    {
-        f4v acc[2][NT];
+        __syncthreads();
+        if (!live) return;
+        const cx<float>* Fh = (const cx<float>*)Fh_;
+        // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs.  The operator loads
+        // of the next kPre steps are in flight while a step runs.
+        constexpr int kPre = NT >= 4 ? 4 : 1;
+        uint2 ring[kPre][2];
+        auto loadB = [&](int s0, uint2(&dst)[2]) {
+            const int sc = min(s0 + lg, Nd - 1);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a) dst[a] = ld_nt8(Fh + (frow + sc) * ldF + pc[a]);
+        };
 #pragma unroll
-            for (int n = 0; n < NT; ++n) acc[a][n] = f4v{0.f, 0.f, 0.f, 0.f};
-
-        if constexpr (MODE == kF32) {
-            const cx<float>* Fh = (const cx<float>*)Fh_;
-            // K step: 4 sensor rows (one per lane group) x (re, im): two MFMAs.  The operator
-            // loads of the next kPre steps are in flight while a step runs.
-            constexpr int kPre = NT >= 4 ? 4 : 1;
-            uint2 ring[kPre][2];
-            auto loadB = [&](int s0, uint2(&dst)[2]) {
-                const int sc = min(s0 + lg, Nd - 1);
+        for (int j = 0; j < kPre; ++j)
+            if (4 * j < Nd) loadB(4 * j, ring[j]);
+        for (int sb = 0; sb < Nd; sb += 4 * kPre) {
 #pragma unroll
-                for (int a = 0; a < 2; ++a) dst[a] = ld_nt8(Fh + (frow + sc) * ldF + pc[a]);
-            };
+            for (int j = 0; j < kPre; ++j) {
+                const int s0 = sb + 4 * j;
+                if (s0 >= Nd) break;
+                const int s = s0 + lg;
+                const bool sv = s < Nd;
+                cx<float> b[2];
 #pragma unroll
-            for (int j = 0; j < kPre; ++j)
-                if (4 * j < Nd) loadB(4 * j, ring[j]);
-            for (int sb = 0; sb < Nd; sb += 4 * kPre) {
+                for (int a = 0; a < 2; ++a)
+                    b[a] = sv ? cx<float>{__uint_as_float(ring[j][a].x), __uint_as_float(ring[j][a].y)}
+                              : cx<float>{0.f, 0.f};
+                if (s0 + 4 * kPre < Nd) loadB(s0 + 4 * kPre, ring[j]);
 #pragma unroll
-                for (int j = 0; j < kPre; ++j) {
-                    const int s0 = sb + 4 * j;
-                    if (s0 >= Nd) break;
-                    const int s = s0 + lg;
-                    const bool sv = s < Nd;
-                    cx<float> b[2];
+                for (int n = 0; n < NT; ++n) {
+                    // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
+                    const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
+                    const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
+                    const bool imrow = li & 1;
+                    const float a0 = imrow ? dim : dre;   // pairs with Re F
+                    const float a1 = imrow ? -dre : dim;  // pairs with Im F
 #pragma unroll
-                    for (int a = 0; a < 2; ++a)
-                        b[a] = sv ? cx<float>{__uint_as_float(ring[j][a].x), __uint_as_float(ring[j][a].y)}
-                                  : cx<float>{0.f, 0.f};
-                    if (s0 + 4 * kPre < Nd) loadB(s0 + 4 * kPre, ring[j]);
-#pragma unroll
-                    for (int n = 0; n < NT; ++n) {
-                        // A row li: rhs n*8 + li/2, part li&1 of the result; K = (s, c)
-                        const uint2 dv = dsh[(n * 8 + (li >> 1)) * Ndp + (sv ? s : 0)];
-                        const float dre = sv ? __uint_as_float(dv.x) : 0.f, dim = sv ? __uint_as_float(dv.y) : 0.f;
-                        const bool imrow = li & 1;
-                        const float a0 = imrow ? dim : dre;   // pairs with Re F
-                        const float a1 = imrow ? -dre : dim;  // pairs with Im F
-#pragma unroll
-                        for (int a = 0; a < 2; ++a) {
-                            acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
-                            acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
-                        }
+                    for (int a = 0; a < 2; ++a) {
+                        acc[a][n] = mfma_f32(a0, b[a].re, acc[a][n]);
+                        acc[a][n] = mfma_f32(a1, b[a].im, acc[a][n]);
                     }
                 }
             }
-        } else {
-            for (int s0 = 0; s0 < Nd; s0 += 16) {
+        }
+    } else {
+        constexpr int KH = c_phase_sensors(NT);  // sensors staged per phase
+        constexpr int GS = c_gp_row_bytes(NT);
+        static_assert(KH >= 16 && NT * 8 * GS <= 65536, "phase staging fits 64 KB");
+        // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im).
+        // Raw operator words of one step: a bf16 pair, or the FP32 (re, im) (split when used).
+        constexpr int WPE = MODE == kSplit ? 2 : 1;
+        struct Raw {
+            uint32_t w[2][4][WPE];
+        };
+        auto load_step = [&](int s0, Raw& raw) {
+            const uint32_t* Fh = (const uint32_t*)Fh_;
+            const cx<float>* Fh32 = (const cx<float>*)Fh_;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int s = s0 + 4 * lg + k;
+                    if constexpr (MODE == kBF16) {
+                        raw.w[a][k][0] = (s < Nd) ? ld_nt4(Fh + (frow + s) * ldF + pc[a]) : 0u;
+                    } else {
+                        const uint2 w = (s < Nd) ? ld_nt8(Fh32 + (frow + s) * ldF + pc[a]) : uint2{0u, 0u};
+                        raw.w[a][k][0] = w.x;
+                        raw.w[a][k][WPE - 1] = w.y;
+                    }
+                }
+        };
+        Raw cur, nxt;
+        if constexpr (PF > 0)
+            if (live) load_step(0, cur);
+        constexpr int kGU = 2;  // staged groups per thread in flight
+        for (int sb = 0; sb < Nd; sb += KH) {
+            const int ng = min(KH, Ndp - sb) >> 2;  // groups of 4 sensors in this phase
+            const int total = NT * 8 * ng;
+            if (sb > 0) __syncthreads();  // every wave is done with the previous phase
+            for (int e0 = threadIdx.x; e0 < total; e0 += kGU * 64 * W) {
+                cx<float> v[kGU][4];
+#pragma unroll
+                for (int u = 0; u < kGU; ++u) {
+                    const int e = e0 + u * 64 * W;
+                    const int r = e / ng, s = sb + 4 * (e % ng);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        v[u][i] = cx<float>{0.f, 0.f};
+                        if (e < total && r < nb && s + i < Nd)
+                            v[u][i] = dh[(int64_t)r * dh_batch + (int64_t)f * Nd + s + i];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kGU; ++u) {
+                    const int e = e0 + u * 64 * W;
+                    if (e < total) {
+                        const int r = e / ng, g = e % ng;
+                        u32x4 p[4];  // real-row hi, lo; imaginary-row hi, lo
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const uint2 h = split_bf16_hw(__float_as_uint(v[u][i].re), __float_as_uint(v[u][i].im));
+                            // K items (re F, im F) pair with (Re d, Im d) for the real row, (Im d,
+                            // -Re d) for the imaginary row
+                            p[0][i] = h.x;
+                            p[1][i] = h.y;
+                            p[2][i] = bf_im_negre(h.x);
+                            p[3][i] = bf_im_negre(h.y);
+                        }
+                        u32x4* dst = reinterpret_cast<u32x4*>(smem_raw + r * GS + g * 64);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) dst[k] = p[k];
+                    }
+                }
+            }
+            __syncthreads();
+            if (!live) continue;
+            const int send = min(sb + KH, Nd);
+            for (int s0 = sb; s0 < send; s0 += 16) {
                 if constexpr (PF > 0) {
                     if (s0 + 16 < Nd) load_step(s0 + 16, nxt);
                 } else {
@@ -532,20 +599,12 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
                             bl[a][k] = h.y;
                         }
                     }
+                const int gq = ((s0 - sb) >> 2) + lg;  // this lane group's sensor group in the phase
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
                     const int r = n * 8 + (li >> 1);
-                    const bool imrow = li & 1;
-                    u32x4 ah, al;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int s = s0 + 4 * lg + k;  // < Ndp; zero-filled past Nd
-                        const uint2 dv = dsh[r * Ndp + s];
-                        // K items (re F, im F) pair with (Re d, Im d) for the real row, (Im d, -Re d)
-                        // for the imaginary row
-                        ah[k] = imrow ? bf_im_negre(dv.x) : dv.x;
-                        al[k] = imrow ? bf_im_negre(dv.y) : dv.y;
-                    }
+                    const u32x4* pa = reinterpret_cast<const u32x4*>(smem_raw + r * GS + gq * 64 + (li & 1) * 32);
+                    const u32x4 ah = pa[0], al = pa[1];
 #pragma unroll
                     for (int a = 0; a < 2; ++a) {
                         acc[a][n] = mfma_bf16(ah, b[a], acc[a][n]);
@@ -556,23 +615,23 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
                 if constexpr (PF > 0) cur = nxt;
             }
         }
-        // C[4 lg + v][li]: result row 4 lg + v -> rhs n*8 + 2 lg + v/2, part v&1; column p = tile + li
+        if (!live) return;
+    }
+    // C[4 lg + v][li]: result row 4 lg + v -> rhs n*8 + 2 lg + v/2, part v&1; column p = tile + li
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int p = pbase + 16 * a + li;
-            if (p >= Nm || (a == 1 && !tile1)) continue;
+    for (int a = 0; a < 2; ++a) {
+        const int p = pbase + 16 * a + li;
+        if (p >= Nm || (a == 1 && !tile1)) continue;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
+        for (int n = 0; n < NT; ++n) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = n * 8 + 2 * lg + h;
-                    if (r < nb) {
-                        // not read again by this launch: non-temporal store
-                        typedef float f2v __attribute__((ext_vector_type(2)));
-                        const f2v w = {acc[a][n][2 * h], acc[a][n][2 * h + 1]};
-                        __builtin_nontemporal_store(
-                            w, reinterpret_cast<f2v*>(mo + (int64_t)r * mo_batch + (int64_t)f * ldv + p));
-                    }
+            for (int h = 0; h < 2; ++h) {
+                const int r = n * 8 + 2 * lg + h;
+                if (r < nb) {
+                    // not read again by this launch: non-temporal store
+                    typedef float f2v __attribute__((ext_vector_type(2)));
+                    const f2v w = {acc[a][n][2 * h], acc[a][n][2 * h + 1]};
+                    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(mo + (int64_t)r * mo_batch + (int64_t)f * ldv + p));
                 }
             }
         }
@@ -580,8 +639,9 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
 }
 
 // =========================================================================================
-size_t sbgemm_c_lds(int nb, int Nd) {
+size_t sbgemm_c_lds(int nb, int Nd, bool bf) {
     const int NT = nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8));
+    if (bf) return (size_t)NT * 8 * c_gp_row_bytes(NT);
     return (size_t)NT * 8 * ((Nd + 15) & ~15) * 8;
 }
 
@@ -603,9 +663,10 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     const int CS = n_span_cols(st, Nm, nfreq);  // the single-vector kernel's spans (multiples of 256 columns)
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
+    const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
     const bool occ2 = var == 4 && NT >= 4;
     const bool wide = occ2 || (var == 2 ? false : (var == 3 ? true : (int64_t)nspan * nfreq >= kWideGrid));
-    const size_t lds = sbgemm_n_lds(NT, chunk_of(NT, wide));
+    const size_t lds = sbgemm_n_lds(NT, chunk_of(NT, wide), mode != kF32);
     dim3 grid(nspan, nfreq), block(kGemmThreads);
     const cx<float>* m = (const cx<float>*)mh;
     cx<float>* p = (cx<float>*)part;
@@ -621,7 +682,6 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
         else                                                                       \
             BT_GN_K(BFV, NTV, (Chunk<NTV, false>::value), 4);                      \
     } while (0)
-    const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
 #define BT_GN_MODE(NTV)                     \
     do {                                    \
         if (mode == kBF16) BT_GN(kBF16, NTV);   \
@@ -655,7 +715,7 @@ hipError_t launch_sbgemm_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
                            bool split, int var) {
     if (st == Stor::C128 || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
-    const size_t lds = sbgemm_c_lds(nb, Nd);
+    const size_t lds = sbgemm_c_lds(nb, Nd, st == Stor::BF16 || split);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     int W, PF;
     c_variant(var, NT, W, PF);

@@ -344,6 +344,24 @@ class GpuExecutor:
                 self.ws[(name, level)] = [torch.empty(nb, dtype=torch.uint8, device="cuda")
                                           for _ in range(n_streams)]
         self.pinned = _PinnedSlots(torch, 8 * 12 * MAX_BATCH)
+        self.max_batch = int(max_batch)
+
+    def autotune(self, reps=2, allow_split=True):
+        """Pick the kernel variants of every operator, before graphs are captured (a graph
+        keeps the kernels it was captured with): the single-vector kernels and transforms of
+        all operators, and for the stored FP32 / BF16 operators the matrix-core kernels of each
+        right-hand-side bucket up to ``max_batch`` (FP32 storage may take the split-BF16 matrix
+        cores, whose products stay within the FP32 accuracy class).  Returns the choices."""
+        from . import btoep_autotune, btoep_autotune_gemm
+        out = {}
+        for level, table in (("lo", self.ops), ("hi", self.ops_hi)):
+            for name, op in table.items():
+                res = {"single": btoep_autotune(op, reps=reps)}
+                if op.storage != "f64":
+                    res["gemm"] = {k: btoep_autotune_gemm(op, k, allow_split=allow_split, reps=reps)
+                                   for k in (8, 16, 32, 64) if k <= self.max_batch}
+                out[(name, level)] = res
+        return out
 
     def _op(self, name, hi):
         return self.ops_hi[name] if hi else self.ops[name]
