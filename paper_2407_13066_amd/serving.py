@@ -346,12 +346,15 @@ class GpuExecutor:
         self.pinned = _PinnedSlots(torch, 8 * 12 * MAX_BATCH)
         self.max_batch = int(max_batch)
 
-    def autotune(self, reps=2, allow_split=True):
+    def autotune(self, reps=2, allow_split=False):
         """Pick the kernel variants of every operator, before graphs are captured (a graph
         keeps the kernels it was captured with): the single-vector kernels and transforms of
         all operators, and for the stored FP32 / BF16 operators the matrix-core kernels of each
-        right-hand-side bucket up to ``max_batch`` (FP32 storage may take the split-BF16 matrix
-        cores, whose products stay within the FP32 accuracy class).  Returns the choices."""
+        right-hand-side bucket up to ``max_batch``.  ``allow_split`` lets FP32 storage take the
+        split-BF16 matrix cores: their products stay within the FP32 apply tolerance, but
+        their larger error (a few 1e-6 instead of ~1e-6) enters the refinement contraction of
+        CG requests squared (eps^2 lambda_max / prior precision), which ill-conditioned
+        systems cannot afford, so it is off by default.  Returns the choices."""
         from . import btoep_autotune, btoep_autotune_gemm
         out = {}
         for level, table in (("lo", self.ops), ("hi", self.ops_hi)):

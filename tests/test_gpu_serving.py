@@ -60,6 +60,8 @@ def run_mix(bt, use_graphs, with_hi, kinds, n, noise_prec, prior_prec, rtol, see
     gen = torch.Generator(device="cuda").manual_seed(seed)
     blocks, ops, ops_hi = build_ops(bt, rng, with_hi)
     ex = GpuExecutor(ops, n_streams=2, max_batch=16, use_graphs=use_graphs, ops_hi=ops_hi)
+    tuned = ex.autotune(reps=1)   # the kernels the mix runs are the tuned ones
+    assert all(not t["split"] for res in tuned.values() for t in res.get("gemm", {}).values())
     srv = Server(ex, hbm_budget=1 << 30, max_batch=16, n_streams=2)
     arrivals = []
     for i in range(n):
