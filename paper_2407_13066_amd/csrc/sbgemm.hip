@@ -36,6 +36,8 @@
 //   A (16 x K): lane holds row i, K group g;  B (K x 16): lane holds column i, K group g;
 //   C (16 x 16): lane holds C[4 g + v][i], v = 0..3.
 // Any fixed assignment of K indices to (group, item) is valid as long as A and B agree.
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -61,16 +63,23 @@ struct Chunk {
 // With several tiles the vector side is staged as ready-made B-operand patterns (16 bytes per
 // column instead of 8, see k_sbgemm_n), so the chunk holds 128 / NT columns.
 static constexpr bool pat_of(int NT, int ch) { return NT >= 2 && ch * NT <= 128; }
-// Row stride (bytes) of the grouped pattern blocks of BF16 / split staging: 64 bytes per group
-// of 4 columns plus one spare group.
-static constexpr int gp_row_bytes(int ch) { return 16 * ch + 64; }
+// BF16 / split staging of operand patterns ("slot layout"): for a tile n of 8 right-hand sides
+// and a group g of 4 K columns (or sensors), a 256-byte block of 16 slots, slot i holding the
+// 4 pattern words that lane li = i ^ swizzle(g) needs for its MFMA operand: one block per
+// (n, g) for the high parts and, a plane further on, one for the remainders.  The 16 lanes of a
+// lane group read one block (256 contiguous bytes: no bank conflicts in any lane grouping);
+// the swizzle moves the group's two low bits into slot bits 0 and 2 so that the scattered
+// 4-byte writes of the staging hit distinct banks across 32 lanes.
+__device__ __forceinline__ int pat_slot(int i, int g) { return i ^ ((g & 1) | ((g & 2) << 1)); }
+// Bytes of one staged plane for NT tiles and G groups; a buffer holds two planes.
+static constexpr int pat_plane_bytes(int NT, int G) { return NT * G * 256; }
 static constexpr int chunk_of(int NT, bool wide) { return NT >= 2 ? 128 / NT : (wide ? 256 : 64); }
 static_assert(Chunk<1, true>::value == chunk_of(1, true) && Chunk<1, false>::value == chunk_of(1, false) &&
                   Chunk<2, true>::value == chunk_of(2, true) && Chunk<4, false>::value == chunk_of(4, false) &&
                   Chunk<8, true>::value == chunk_of(8, true),
               "host and kernel chunk sizes");
 static size_t sbgemm_n_lds(int NT, int ch, bool bf) {
-    if (pat_of(NT, ch)) return bf ? (size_t)2 * NT * 8 * gp_row_bytes(ch) : (size_t)2 * NT * 8 * (ch + 1) * 16;
+    if (pat_of(NT, ch)) return bf ? (size_t)2 * 2 * pat_plane_bytes(NT, ch / 4) : (size_t)2 * NT * 8 * (ch + 1) * 16;
     return (size_t)2 * NT * 8 * (ch + 2) * 8;
 }
 // Launches with fewer (span, frequency) workgroups than this keep 64-column chunks, whose
@@ -126,10 +135,8 @@ __device__ __forceinline__ uint32_t bf_im_negre(uint32_t x) { return ((x >> 16) 
 // staged (8 bytes: float complex, or (hi, lo) packed bf16 pairs; row stride kChunk + 2) or,
 // with PAT, both B-operand patterns a lane can need: FP32 mode 16 bytes per column (row stride
 // kChunk + 1), lanes of even result column (real part) taking the first 8 bytes, lanes of odd
-// column the second; BF16 and split modes (GP) one 64-byte block per group of 4 columns,
-// [real-column hi x4 | real-column lo x4 | imaginary-column hi x4 | imaginary-column lo x4],
-// so that a lane's B operands are two aligned 16-byte LDS reads (row stride 64 kChunk / 4 +
-// 64 bytes, which keeps a wave's reads free of bank conflicts).
+// column the second; BF16 and split modes (GP) the slot layout (pat_slot): a lane's B operands
+// are two aligned 16-byte LDS reads, and the inner loop has no pattern arithmetic.
 template <int MODE, int NT, int kChunk, int OCC>
 __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OCC))) void k_sbgemm_n(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
                                                            const cx<float>* __restrict__ mh, int64_t ldv,
@@ -137,10 +144,10 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                                                            int CS, int nspan, int nfreq, int64_t part_batch) {
     constexpr bool PAT = pat_of(NT, kChunk);
     constexpr bool BF = MODE != kF32;                 // vector side staged as bf16 (hi, lo)
-    constexpr bool GP = PAT && BF;                    // grouped 64-byte pattern blocks
+    constexpr bool GP = PAT && BF;                    // slot layout of ready-made patterns
     constexpr int SB = MODE == kBF16 ? 4 : 8;         // bytes of a stored operator entry
     constexpr int LDR = PAT ? kChunk + 1 : kChunk + 2;  // row stride (entries) of a staged chunk
-    constexpr int GS = gp_row_bytes(kChunk);          // row stride (bytes) of a GP chunk
+    constexpr int GPL = pat_plane_bytes(NT, kChunk / 4);  // bytes of a GP plane
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint2* buf = reinterpret_cast<uint2*>(smem_raw);   // [2][NT*8][LDR] 8-byte entries
     uint4* buf4 = reinterpret_cast<uint4*>(smem_raw);  // [2][NT*8][LDR] 16-byte entries (PAT)
@@ -170,21 +177,24 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
     };
     auto stage_store = [&](int which, const cx<float>* v) {
         if constexpr (GP) {
-            // entry (r, q) -> word q % 4 of the four 16-byte planes of block (r, q / 4); the loads
-            // above stay lane-contiguous (coalesced), the scatter happens in the LDS writes
+            // entry (r, q) -> word q % 4 of the slots of lanes 2 (r % 8) (real-part column) and
+            // 2 (r % 8) + 1 (imaginary-part column) in block (r / 8, q / 4); the loads above stay
+            // lane-contiguous (coalesced), the scatter happens in the LDS writes
 #pragma unroll
             for (int i = 0; i < kPer; ++i) {
                 const int e = threadIdx.x + i * kGemmThreads;
                 const int r = e / kChunk, q = e % kChunk;
+                const int g = q >> 2;
                 const uint2 h = split_bf16_hw(__float_as_uint(v[i].re), __float_as_uint(v[i].im));
-                uint32_t* dst = reinterpret_cast<uint32_t*>(smem_raw + (size_t)which * rows_per_buf * GS + r * GS +
-                                                            (q >> 2) * 64 + (q & 3) * 4);
+                unsigned char* blk = smem_raw + (size_t)which * 2 * GPL + ((r >> 3) * (kChunk / 4) + g) * 256 + (q & 3) * 4;
                 // (Re m, -Im m) pairs with (Re F, Im F) for a real-part column, (Im m, Re m) for
                 // an imaginary-part column
-                dst[0] = bf_re_negim(h.x);
-                dst[4] = bf_re_negim(h.y);
-                dst[8] = bf_im_re(h.x);
-                dst[12] = bf_im_re(h.y);
+                uint32_t* d0 = reinterpret_cast<uint32_t*>(blk + pat_slot(2 * (r & 7), g) * 16);
+                uint32_t* d1 = reinterpret_cast<uint32_t*>(blk + pat_slot(2 * (r & 7) + 1, g) * 16);
+                d0[0] = bf_re_negim(h.x);
+                d0[GPL / 4] = bf_re_negim(h.y);
+                d1[0] = bf_im_re(h.x);
+                d1[GPL / 4] = bf_im_re(h.y);
             }
             return;
         }
@@ -349,10 +359,11 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
                             const bool imcol = li & 1;
                             u32x4 bh, bl;
                             if constexpr (GP) {
+                                const int g = q0 >> 2;
                                 const u32x4* pb = reinterpret_cast<const u32x4*>(
-                                    smem_raw + (size_t)(c & 1) * rows_per_buf * GS + r * GS + (q0 >> 2) * 64 + imcol * 32);
+                                    smem_raw + (size_t)(c & 1) * 2 * GPL + (n * (kChunk / 4) + g) * 256 + pat_slot(li, g) * 16);
                                 bh = pb[0];
-                                bl = pb[1];
+                                bl = pb[GPL / 16];
                             } else {
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) {
@@ -407,21 +418,19 @@ __global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(OC
 // in LDS (as the A operand's source), kStageUnroll loads per thread in flight at a time.
 //   FP32 mode: all Nd sensors at once, one 8-byte entry per (r, s); a lane forms the
 //     imaginary-row pattern itself.
-//   BF16 / split modes (GP): both A-operand patterns ready-made, one 64-byte block per
-//     (r, group of 4 sensors) = [real-row hi x4 | real-row lo x4 | imaginary-row hi x4 |
-//     imaginary-row lo x4], so a lane's A operands are two aligned 16-byte LDS reads and the
-//     inner loop has no pattern arithmetic; staged c_phase_sensors(NT) sensors at a time (the
-//     LDS bound), with a barrier between phases.  Row stride 16 KH + 64 bytes keeps a wave's
-//     reads free of bank conflicts.
+//   BF16 / split modes: both A-operand patterns ready-made in the slot layout (pat_slot; the
+//     rows of a tile are (right-hand side, real / imaginary part) as the lanes li), so a lane's
+//     A operands are two aligned 16-byte LDS reads and the inner loop has no pattern
+//     arithmetic; staged c_phase_sensors(NT) sensors at a time (the LDS bound), with a barrier
+//     between phases.
 // PF (BF16 and split modes): 1 issues the operator loads of the next K step before the current
 // step's matrix-core work, so one more step of the operator stream is in flight per wave; the
 // first step's loads are then issued before the staging.
 constexpr int kStageUnroll = 8;
 static constexpr int c_phase_sensors(int NT) {
-    // largest multiple of 16 with NT * 8 * (16 KH + 64) <= 64 KB
-    return ((65536 / (NT * 8) - 64) / 16) / 16 * 16;
+    // largest multiple of 16 with two planes of NT tiles x KH / 4 groups within 64 KB
+    return (65536 / (2 * NT * 256)) * 4 / 16 * 16;
 }
-static constexpr int c_gp_row_bytes(int NT) { return 16 * c_phase_sensors(NT) + 64; }
 
 template <int MODE, int NT, int W, int PF>
 __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh_, int64_t ldF, int Nd, int Nm,
@@ -508,9 +517,10 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
             }
         }
     } else {
-        constexpr int KH = c_phase_sensors(NT);  // sensors staged per phase
-        constexpr int GS = c_gp_row_bytes(NT);
-        static_assert(KH >= 16 && NT * 8 * GS <= 65536, "phase staging fits 64 KB");
+        static_assert(c_phase_sensors(NT) >= 16 && 2 * pat_plane_bytes(NT, c_phase_sensors(NT) / 4) <= 65536,
+                      "phase staging fits 64 KB");
+        const int KH = min(c_phase_sensors(NT), Ndp);  // sensors staged per phase
+        const int GPL = NT * (KH / 4) * 256;           // bytes of a staged plane
         // K step: 16 sensor rows; lane group lg holds rows 4 lg .. 4 lg + 3, items (re, im).
         // Raw operator words of one step: a bf16 pair, or the FP32 (re, im) (split when used).
         constexpr int WPE = MODE == kSplit ? 2 : 1;
@@ -571,9 +581,13 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
                             p[2][i] = bf_im_negre(h.x);
                             p[3][i] = bf_im_negre(h.y);
                         }
-                        u32x4* dst = reinterpret_cast<u32x4*>(smem_raw + r * GS + g * 64);
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) dst[k] = p[k];
+                        unsigned char* blk = smem_raw + ((r >> 3) * (KH / 4) + g) * 256;
+                        u32x4* d0 = reinterpret_cast<u32x4*>(blk + pat_slot(2 * (r & 7), g) * 16);
+                        u32x4* d1 = reinterpret_cast<u32x4*>(blk + pat_slot(2 * (r & 7) + 1, g) * 16);
+                        d0[0] = p[0];
+                        d0[GPL / 16] = p[1];
+                        d1[0] = p[2];
+                        d1[GPL / 16] = p[3];
                     }
                 }
             }
@@ -602,9 +616,9 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
                 const int gq = ((s0 - sb) >> 2) + lg;  // this lane group's sensor group in the phase
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
-                    const int r = n * 8 + (li >> 1);
-                    const u32x4* pa = reinterpret_cast<const u32x4*>(smem_raw + r * GS + gq * 64 + (li & 1) * 32);
-                    const u32x4 ah = pa[0], al = pa[1];
+                    const u32x4* pa =
+                        reinterpret_cast<const u32x4*>(smem_raw + (n * (KH / 4) + gq) * 256 + pat_slot(li, gq) * 16);
+                    const u32x4 ah = pa[0], al = pa[GPL / 16];
 #pragma unroll
                     for (int a = 0; a < 2; ++a) {
                         acc[a][n] = mfma_bf16(ah, b[a], acc[a][n]);
@@ -641,7 +655,7 @@ __global__ __launch_bounds__(64 * W) void k_sbgemm_c(const void* __restrict__ Fh
 // =========================================================================================
 size_t sbgemm_c_lds(int nb, int Nd, bool bf) {
     const int NT = nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8));
-    if (bf) return (size_t)NT * 8 * c_gp_row_bytes(NT);
+    if (bf) return (size_t)2 * pat_plane_bytes(NT, std::min(c_phase_sensors(NT), (Nd + 15) & ~15) / 4);
     return (size_t)NT * 8 * ((Nd + 15) & ~15) * 8;
 }
 
