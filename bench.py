@@ -762,7 +762,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling PMC byte counters)")
     ap.add_argument("--calibrate-read", action="store_true",
-                    help="only measure the streaming-read rate of one 22 GB array (the memory system's read ceiling)")
+                    help="only measure the streaming-read and streaming-write rates of one 22 GB array (the memory system's ceilings)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline H timing (for profiler runs)")
     ap.add_argument("--f64-only", action="store_true",
@@ -821,7 +821,9 @@ def main():
     if args.calibrate_read:
         nbytes = 22 * 10 ** 9
         res = bt.btoep_read_bandwidth(nbytes, reps=5)
-        print(json.dumps({"calibration": "streaming read", "bytes": nbytes, **res}))
+        wres = bt.btoep_write_bandwidth(nbytes, reps=5)
+        print(json.dumps({"calibration": "streaming read", "bytes": nbytes, **res,
+                          "write": {"calibration": "streaming write", "bytes": nbytes, **wres}}))
         return 0
 
     if args.serving_only:

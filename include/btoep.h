@@ -462,6 +462,18 @@ btoep_status btoep_cg_end(btoep_cg cg);
 btoep_status btoep_read_bandwidth(size_t bytes, int reps, void* stream, double* best_ms, double* best_gbs,
                                   double* mean_gbs);
 
+/*
+ * Measurement support: writes one device array of `bytes` (>= 1 MiB) with non-temporal 8- or
+ * 16-byte stores, `reps` times for each of six launch shapes (store width 8 or 16 bytes, 4, 8
+ * or 16 workgroups per CU) on `stream` (the current device), and returns, for the shape with
+ * the lowest mean, the best time and the best and mean write rates (GB/s = 1e9 bytes/s): the
+ * ceiling of the kernels whose traffic is mostly result writes (the adjoint products of
+ * several right-hand sides, the forward transform).  Allocates and frees the array
+ * (synchronises the device).  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+btoep_status btoep_write_bandwidth(size_t bytes, int reps, void* stream, double* best_ms, double* best_gbs,
+                                   double* mean_gbs);
+
 /* Static text for a status code. */
 const char* btoep_status_string(btoep_status s);
 

@@ -126,6 +126,8 @@ def load_library(path=LIB_PATH):
         "btoep_cg_workspace_size": ([vp, vp, i64, ctypes.POINTER(sz)], st),
         "btoep_read_bandwidth": ([sz, ctypes.c_int, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                   ctypes.POINTER(dbl)], st),
+        "btoep_write_bandwidth": ([sz, ctypes.c_int, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                   ctypes.POINTER(dbl)], st),
         "btoep_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "btoep_last_error": ([vp], ctypes.c_char_p),
     }
@@ -407,6 +409,14 @@ def btoep_read_bandwidth(nbytes, reps=5, stream=None):
     ms, best, mean = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(load_library().btoep_read_bandwidth(int(nbytes), int(reps), _stream(stream), ctypes.byref(ms),
                                                ctypes.byref(best), ctypes.byref(mean)), "btoep_read_bandwidth")
+    return {"best_ms": round(ms.value, 4), "best_GBs": round(best.value, 1), "mean_GBs": round(mean.value, 1)}
+
+
+def btoep_write_bandwidth(nbytes, reps=5, stream=None):
+    """Streaming-write rate of one device array of ``nbytes`` (btoep_write_bandwidth)."""
+    ms, best, mean = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().btoep_write_bandwidth(int(nbytes), int(reps), _stream(stream), ctypes.byref(ms),
+                                                ctypes.byref(best), ctypes.byref(mean)), "btoep_write_bandwidth")
     return {"best_ms": round(ms.value, 4), "best_GBs": round(best.value, 1), "mean_GBs": round(mean.value, 1)}
 
 

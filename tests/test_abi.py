@@ -150,3 +150,15 @@ def test_gemm_tuning_arguments_rejected(lib):
     assert lib.btoep_set_gemm(None, 0) == 1
     assert lib.btoep_set_gemm_variants(None, 8, 0, 0) == 1
     assert lib.btoep_autotune_gemm(None, 8, 1, 3, None, None) == 1
+
+
+def test_bandwidth_calibration_arguments_rejected(lib):
+    """Sizes below 1 MiB, no repetitions or missing outputs are rejected before any device call."""
+    out = [ctypes.c_double() for _ in range(3)]
+    refs = [ctypes.byref(o) for o in out]
+    for fn in (lib.btoep_read_bandwidth, lib.btoep_write_bandwidth):
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 3
+        assert fn(1024, 3, None, *refs) == 1
+        assert fn(1 << 24, 0, None, *refs) == 1
+        assert fn(1 << 24, 3, None, None, refs[1], refs[2]) == 1
