@@ -300,6 +300,33 @@ def test_extreme_sensor_and_parameter_counts(bt, shape, storage, k):
     assert e.value.status == 4
 
 
+@pytest.mark.parametrize("storage", ["f32split", "bf16"])
+def test_adjoint_products_staged_in_phases(bt, storage):
+    """BF16 / split adjoint products stage the data spectra in phases of at most 64 sensors (eight
+    tiles) or 128 (four tiles): Nd = 150 takes three and two phases, with a ragged last one, in every
+    adjoint variant; F^T and H against the oracle."""
+    rng = np.random.default_rng(83)
+    Nt, Nd, Nm = 9, 150, 700
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / 3.0)[:, None, None]
+    op = make(bt, blocks, storage)
+    tol = TOL[storage]
+    for k in (20, 40):
+        print("case adjoint phases", storage, k, flush=True)
+        D = rng.standard_normal((k, Nt, Nd)).astype(np.float32)
+        M = rng.standard_normal((k, Nt, Nm)).astype(np.float32)
+        FTD_ref = oracle.apply_FT(blocks, D.astype(np.float64))
+        HM_ref = oracle.apply_H(blocks, M[[0, k - 1]].astype(np.float64), 2.0, 0.5)
+        for var_c in range(N_GEMM_C_VARIANTS):
+            bt.btoep_set_gemm_variants(op, k, 0, var_c)
+            FTD = bt.btoep_apply_FT(op, to_dev(D, torch.float32)).double().cpu().numpy()
+            for r in range(k):
+                assert oracle.rel_l2(FTD[r], FTD_ref[r]) <= tol, ("FT", k, var_c, r)
+            HM = bt.btoep_apply_H(op, to_dev(M, torch.float32), 2.0, 0.5)[[0, k - 1]].double().cpu().numpy()
+            for i in range(2):
+                assert oracle.rel_l2(HM[i], HM_ref[i]) <= tol, ("H", k, var_c, i)
+    op.destroy()
+
+
 # matrix-core kernel variants the library offers (forward, adjoint)
 N_GEMM_N_VARIANTS, N_GEMM_C_VARIANTS = 5, 5
 
