@@ -120,8 +120,9 @@ hipError_t launch_sbgemv_c(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
 // one launch (FP32 or BF16 storage only).  sbgemm_c needs sbgemm_c_lds(nb, Nd, bf) <= 64 KB
 // (bf: BF16 storage or the split mode, whose staging is phased and fits any Nd).
 size_t sbgemm_c_lds(int nb, int Nd, bool bf);
-// The N launcher takes at most kGemmNMax right-hand sides (an 8-tile N kernel measured slower
-// than two 4-tile launches); callers group larger batches.
+// Right-hand sides per N launch in the narrow/wide-chunk variants and in the FP64 kernels
+// (four 16-column result tiles); the other FP32 / BF16 variants take up to kMaxBatch in one
+// eight-tile pass (sbgemm_n_group); callers group larger batches.
 constexpr int kGemmNMax = 32;
 // `split` (FP32 storage only): run the products on the BF16 matrix cores with the operator and
 // the vectors split into BF16 high parts and remainders (three MFMAs per product).

@@ -661,14 +661,15 @@ size_t sbgemm_c_lds(int nb, int Nd, bool bf) {
 
 static int nt_of(int nb) { return nb <= 8 ? 1 : (nb <= 16 ? 2 : (nb <= 32 ? 4 : 8)); }
 
-// Variants of the N kernel: 0 the default (right-hand sides in groups of at most kGemmNMax,
-// wide chunks on launches of >= kWideGrid workgroups), 1 groups of up to 64 (one pass over
-// the operator for up to 64 right-hand sides, eight-tile kernel), 2 / 3 narrow / wide chunks
-// on every launch, 4 as 1 with the register budget of two waves per SIMD instead of four
-// (four or more tiles, whose accumulators and operator prefetch spill at four; below that it
-// equals 1).
+// Variants of the N kernel: 0 the default rule (wide chunks on launches of >= kWideGrid
+// workgroups; more than kGemmNMax right-hand sides in one eight-tile pass, with the two-wave
+// register budget in the BF16 and split modes -- the fastest choices measured at 64), 1 groups
+// of up to 64 (one pass over the operator for up to 64 right-hand sides, eight-tile kernel),
+// 2 / 3 narrow / wide chunks on every launch, in groups of at most kGemmNMax, 4 as 1 with the
+// register budget of two waves per SIMD instead of four (four or more tiles, whose accumulators
+// and operator prefetch spill at four; below that it equals 1).
 int sbgemm_n_variants() { return 5; }
-int sbgemm_n_group(int var) { return (var == 1 || var == 4) ? kMaxBatch : kGemmNMax; }
+int sbgemm_n_group(int var) { return (var == 2 || var == 3) ? kGemmNMax : kMaxBatch; }
 
 hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int Nd, int Nm, const void* mh,
                            int64_t ldv, int64_t mh_batch, int nb, void* part, int nspan, int64_t part_batch,
@@ -678,7 +679,7 @@ hipError_t launch_sbgemm_n(Stor st, const void* Fh, int64_t ldF, int nfreq, int 
     if (nspan != (Nm + CS - 1) / CS) return hipErrorInvalidValue;
     const int NT = nt_of(nb);
     const int mode = st == Stor::BF16 ? kBF16 : (split ? kSplit : kF32);
-    const bool occ2 = var == 4 && NT >= 4;
+    const bool occ2 = (var == 4 || (var == 0 && nb > kGemmNMax && mode != kF32)) && NT >= 4;
     const bool wide = occ2 || (var == 2 ? false : (var == 3 ? true : (int64_t)nspan * nfreq >= kWideGrid));
     const size_t lds = sbgemm_n_lds(NT, chunk_of(NT, wide), mode != kF32);
     dim3 grid(nspan, nfreq), block(kGemmThreads);
