@@ -102,8 +102,9 @@ def test_multi_rhs_full_size(bt, blocks, op32, storage, tol):
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("storage,tol", [("f32split", 1e-5), ("bf16", 3e-3)])
 def test_multi_rhs_full_size_k64(bt, blocks, op32, storage, tol):
-    """k = 64 right-hand sides at full size (the matrix-core kernels' widest tiles, two
-    forward launches of 32): columns 0, 31, 32 and 63 against the oracle."""
+    """k = 64 right-hand sides at full size (the matrix-core kernels' widest tiles, one
+    eight-tile forward pass by the default rule; the adjoint in two staging phases at Nd = 100):
+    columns 0, 31, 32 and 63 against the oracle."""
     print("case full-size k=64", storage, flush=True)
     op = bt.btoep_create(blocks, "bf16" if storage == "bf16" else "f32")
     if storage == "f32split":
