@@ -635,6 +635,68 @@ def cg_benchmark(bt):
     return out
 
 
+def small_case(bt, calls=50):
+    """The small FP64 case (Nt=32, Nd=16, Nm=64; 0.5 MB operator, cache-resident): microseconds
+    per F, F^T and H call (median over `calls` calls, each between HIP events on the launch
+    stream), launched directly and as a graph replay on the same vectors, the full-vector error
+    against the FP64 oracle, and the oracle's own time per call on the host."""
+    import torch
+    import oracle
+    import synth
+    w = synth.WORKLOADS["fp64-small"]
+    Nt, Nd, Nm = w["Nt"], w["Nd"], w["Nm"]
+    blocks = synth.blocks(Nt, Nd, Nm, w["tau"])
+    op = bt.btoep_create(blocks, "f64")
+    m = synth.vectors(1, Nt, Nm, synth.STREAM_M)
+    d = synth.vectors(1, Nt, Nd, synth.STREAM_D)
+    md, dd = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
+    st = torch.cuda.Stream()
+    ref = {"F": oracle.apply_F(blocks, m), "FT": oracle.apply_FT(blocks, d), "H": oracle.apply_H(blocks, m, 1.0, 1.0)}
+    res = {"workload": "fp64-small", "Nt": Nt, "Nd": Nd, "Nm": Nm, "fhat_MB": round(op.info["fhat_bytes"] / 1e6, 3),
+           "calls": calls}
+    for which in ("F", "FT", "H"):
+        x = dd if which == "FT" else md
+        y = torch.empty((1, Nt, Nm if which != "F" else Nd), dtype=torch.float64, device="cuda")
+        ws = torch.empty(bt.btoep_workspace_size(op, which, 1), dtype=torch.uint8, device="cuda")
+        g = bt.ApplyGraph(op, which, 1, 1.0, 1.0, ws=ws)
+        g.launch([x.data_ptr()], [y.data_ptr()], stream=st)
+
+        def direct():
+            bt.btoep_apply_batched_ptrs(op, which, [x.data_ptr()], [y.data_ptr()], 1.0, 1.0, ws=ws, stream=st)
+
+        def replay():
+            g.launch(stream=st)
+        entry = {}
+        for name, fn in (("direct", direct), ("graph", replay)):
+            for _ in range(5):
+                fn()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+            with torch.cuda.stream(st):
+                for a, b in ev:
+                    a.record(st)
+                    fn()
+                    b.record(st)
+            st.synchronize()
+            entry[name + "_us"] = round(1e3 * float(np.median([a.elapsed_time(b) for a, b in ev])), 2)
+        direct()
+        st.synchronize()
+        entry["rel_err"] = oracle.rel_l2(y.cpu().numpy()[0], ref[which][0])
+        g.destroy()
+        res[which] = entry
+    t = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.apply_H(blocks, m, 1.0, 1.0)
+        t.append(time.perf_counter() - t0)
+    res["oracle_H_us"] = round(1e6 * float(np.median(t)), 1)
+    res["tolerance"] = 1e-12
+    op.destroy()
+    log("small FP64 case: " + ", ".join("%s %.1f us direct / %.1f us graph (rel err %.1e)" % (
+        k, res[k]["direct_us"], res[k]["graph_us"], res[k]["rel_err"]) for k in ("F", "FT", "H")) +
+        "; oracle H %.0f us" % res["oracle_H_us"])
+    return res
+
+
 def time_H(bt, op, m, out, ws, stream, steps, warmup, noise_prec, prior_prec):
     """Warm-up, then `steps` H applications bracketed by device synchronisation, with per-kernel
     HIP events on the launch stream.  Returns (ms per H, {kernel: (launches, total ms)})."""
@@ -959,6 +1021,7 @@ def main():
     if not args.no_setup:
         result["setup"] = setup_benchmark(bt, blocks, w["storage"], host_setup_s)
     del blocks
+    result["small_fp64"] = small_case(bt)
     if not args.no_cg:
         result["cg"] = cg_benchmark(bt)
         torch.cuda.empty_cache()
