@@ -15,10 +15,11 @@
 //               A workgroup keeps the whole Nd x 2k accumulator of its span in registers
 //               and streams the right-hand sides through LDS in chunks (256 or 64 columns
 //               for one tile of 8 right-hand sides; 128 / NT columns of ready-made operand
-//               patterns for NT = 2 or 4 tiles).  At most 32 right-hand sides per launch.
+//               patterns for NT = 2, 4 or 8 tiles).  Up to 64 right-hand sides per launch.
 //   C (for F^T): O_f^T (2k x Nm) = D_f^T (2k x 2Nd) Fh_f (2Nd x Nm): the operator is the
 //               B operand, lanes own output columns p, so each result row of 16 p values
-//               is stored as one contiguous run; no reduction across workgroups.
+//               is stored as one contiguous run; no reduction across workgroups.  The data
+//               spectra of the frequency are staged in LDS as ready-made A operands.
 //
 // Three product modes (template parameter MODE):
 //   kF32   FP32 storage on v_mfma_f32_16x16x4_f32 (FP32 operands);
@@ -60,8 +61,8 @@ template <int NT, bool WIDE>
 struct Chunk {
     static constexpr int value = NT >= 2 ? 128 / NT : (WIDE ? 256 : 64);
 };
-// With several tiles the vector side is staged as ready-made B-operand patterns (16 bytes per
-// column instead of 8, see k_sbgemm_n), so the chunk holds 128 / NT columns.
+// With several tiles the vector side is staged as ready-made B-operand patterns (twice the
+// bytes of the plain entries, see k_sbgemm_n), so the chunk holds 128 / NT columns.
 static constexpr bool pat_of(int NT, int ch) { return NT >= 2 && ch * NT <= 128; }
 // BF16 / split staging of operand patterns ("slot layout"): for a tile n of 8 right-hand sides
 // and a group g of 4 K columns (or sensors), a 256-byte block of 16 slots, slot i holding the
