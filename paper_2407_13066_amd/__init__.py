@@ -78,6 +78,10 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OSError("libbtoep.so not built at %s (run __graft_entry__.build())" % path)
+    # torch first: the library then binds to the HIP runtime torch has loaded, so the process
+    # holds one runtime (with the library loaded first, calls into it from a process whose
+    # torch brings its own runtime have failed with "no ROCm-capable device")
+    _torch()
     lib = ctypes.CDLL(path)
     vp, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     st = ctypes.c_int

@@ -77,6 +77,12 @@ void set_err(btoep_op op, const char* what, hipError_t e) {
     snprintf(dst, 512, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
+}  // namespace
+
+void btoep::set_global_error(const char* what, hipError_t e) { set_err(nullptr, what, e); }
+
+namespace {
+
 #define BT_HIP(op, expr)                                  \
     do {                                                  \
         hipError_t e_ = (expr);                           \

@@ -8,6 +8,7 @@
 #include <cstdio>
 
 #include "btoep.h"
+#include "internal.h"
 
 namespace {
 
@@ -79,6 +80,7 @@ extern "C" {
 btoep_status btoep_read_bandwidth(size_t bytes, int reps, void* stream, double* best_ms, double* best_gbs,
                                   double* mean_gbs) {
     if (bytes < (1u << 20) || reps < 1 || !best_ms || !best_gbs || !mean_gbs) return BTOEP_ERR_INVALID_ARG;
+    (void)hipGetLastError();  // an error left by an earlier call must not be taken for a launch failure
     hipStream_t st = (hipStream_t)stream;
     const size_t n = bytes / 16;
     u32x4* p = nullptr;
@@ -126,7 +128,10 @@ btoep_status btoep_read_bandwidth(size_t bytes, int reps, void* stream, double* 
     if (b) (void)hipEventDestroy(b);
     if (p) (void)hipFree(p);
     if (out) (void)hipFree(out);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+    if (e != hipSuccess) {
+        btoep::set_global_error("btoep_read_bandwidth", e);
+        return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+    }
     const double nb = (double)n * 16.0;
     *best_ms = best;
     *best_gbs = nb / (best * 1e-3) / 1e9;
@@ -137,6 +142,7 @@ btoep_status btoep_read_bandwidth(size_t bytes, int reps, void* stream, double* 
 btoep_status btoep_write_bandwidth(size_t bytes, int reps, void* stream, double* best_ms, double* best_gbs,
                                    double* mean_gbs) {
     if (bytes < (1u << 20) || reps < 1 || !best_ms || !best_gbs || !mean_gbs) return BTOEP_ERR_INVALID_ARG;
+    (void)hipGetLastError();  // an error left by an earlier call must not be taken for a launch failure
     hipStream_t st = (hipStream_t)stream;
     const size_t nb = bytes / 16 * 16;
     void* p = nullptr;
@@ -179,7 +185,10 @@ btoep_status btoep_write_bandwidth(size_t bytes, int reps, void* stream, double*
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     if (p) (void)hipFree(p);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+    if (e != hipSuccess) {
+        btoep::set_global_error("btoep_write_bandwidth", e);
+        return e == hipErrorOutOfMemory ? BTOEP_ERR_OUT_OF_MEMORY : BTOEP_ERR_HIP;
+    }
     *best_ms = best;
     *best_gbs = (double)nb / (best * 1e-3) / 1e9;
     *mean_gbs = (double)nb / (sum / reps * 1e-3) / 1e9;

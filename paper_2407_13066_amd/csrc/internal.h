@@ -26,6 +26,9 @@ struct PtrBatch {
 };
 
 enum class Real { F32, F64 };
+
+// Records a failed HIP call as the thread's last error (btoep_last_error(NULL)).
+void set_global_error(const char* what, hipError_t e);
 enum class Stor { C128 = 0, C64 = 1, BF16 = 2 };
 
 // Threads per workgroup of every FFT kernel.
