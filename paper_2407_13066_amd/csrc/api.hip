@@ -413,10 +413,10 @@ btoep_status run_apply(btoep_op op, btoep_which which, int nb, const PtrBatch& i
     void* tmp = ws + w.tmp;
     void* spec = ws + w.spec;
     char* dtmp = ws + w.dtmp;
-    const int Nt = (int)op->Nt, Nd = (int)op->Nd, Nm = (int)op->Nm, nf = (int)op->nfreq;
+    const int Nt = (int)op->Nt, Nd = (int)op->Nd, nf = (int)op->nfreq;
     const int nspan = (int)nspan_of(op);
     const int64_t vh_b = op->nfreq * op->ldv, part_b = op->nfreq * nspan * op->Nd, dh_b = op->nfreq * op->Nd;
-    const int64_t N = op->N, ldv = op->ldv;
+    const int64_t N = op->N;
     const double inv_n = 1.0 / (double)op->N;
     const void* tw = tw_of(op);
     const bool lg = op->fft_long;

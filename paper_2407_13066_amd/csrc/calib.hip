@@ -13,7 +13,6 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kUnroll = 4;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(kThreads) void k_fill(u32x4* __restrict__ p, size_t n) {
