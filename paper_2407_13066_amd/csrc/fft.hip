@@ -744,12 +744,12 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     }
 }
 
-// ---- vector-side transforms with fixed column tiles (FP32, compile-time plans) ------------
+// ---- vector-side transforms with fixed column tiles (FP32 / FP64, compile-time plans) -----
 // The same transforms as k_fft_r2c / k_fft_c2r at their widest tile, with the tile width
 // 2^LOGP a compile-time constant (every index is then shifts and masks) and the two ends of
 // each transform fused with its global memory accesses; the arithmetic counts, not the
 // memory traffic, bounded the general kernels:
-//  - forward: every thread of the first pass loads its butterfly's inputs straight from the
+//  - forward: every thread of the first pass loads its butterflies' inputs straight from the
 //    real rows (z_n = x_{2n} + i x_{2n+1}; the upper half n >= N/2 is the zero padding and is
 //    neither loaded nor added), so the input never passes through LDS; the output bins are
 //    formed in pairs f, N-f, which share both spectrum reads and the twiddle product:
@@ -778,15 +778,28 @@ struct RestPasses<T, DIR, CMAX, TWL, CtPlan<R0, Rs...>> {
 template <typename T>
 using gptr = __attribute__((address_space(1))) T*;
 
-template <typename PL, int LOGP>
+// A complex value stored to a vector-side spectrum row: FP32 runs of >= 64 bytes per row go
+// non-temporal (see put_nt); FP64 values use ordinary 16-byte stores, as the general kernels do.
+template <typename T, int LOGP>
+__device__ __forceinline__ void put_vec(gptr<cx<T>> q, cx<T> v) {
+    if constexpr (sizeof(T) == 4 && (8 << LOGP) >= 64) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(f2v{v.re, v.im}, (gptr<f2v>)q);
+    } else {
+        q->re = v.re;
+        q->im = v.im;
+    }
+}
+
+template <typename T, typename PL, int LOGP>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vr2c(
-    PtrBatch in, int64_t in_row, cx<float>* __restrict__ out, int64_t out_row, int64_t out_batch, int Nt, int ncols,
-    const cx<float>* __restrict__ twg) {
-    typedef float T;
+    PtrBatch in, int64_t in_row, cx<T>* __restrict__ out, int64_t out_row, int64_t out_batch, int Nt, int ncols,
+    const cx<T>* __restrict__ twg) {
     constexpr int N = PL::N, P = 1 << LOGP, R = FirstRadix<PL>::value, NR = N / R;
     constexpr int RSTEP = kFftThreads >> LOGP;  // rows a thread advances per loop step
+    constexpr int NB = (NR * P + kFftThreads - 1) / kFftThreads;  // first-pass butterflies per thread
     constexpr bool TWL = ct_twl<T>(N);
-    static_assert(R % 2 == 0 && NR * P <= kFftThreads, "one first-pass butterfly per thread");
+    static_assert(R % 2 == 0, "the zero padding is the upper half of each first-pass butterfly");
     cx<T>* sh = reinterpret_cast<cx<T>*>(fft_smem);
     const size_t tw_off = (size_t)(N + 1) * P * sizeof(cx<T>);
     const int col0 = column_block() << LOGP;
@@ -794,21 +807,30 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int c = tid & (P - 1), j = tid >> LOGP;  // column; first-pass butterfly / first bin pair
     const bool live = col0 + c < ncols;
     const gptr<const T> xc = (gptr<const T>)static_cast<const T*>(in.at(blockIdx.y)) + min(col0 + c, ncols - 1);
-    // first pass (Ns = 1), butterfly j: inputs n = j + r NR for r < R/2, loaded from rows 2n, 2n+1
-    cx<T> v[R];
-    if (j < NR) {
+    // first pass (Ns = 1), butterflies jb = j + b RSTEP < NR: inputs n = jb + r NR for r < R/2,
+    // loaded from rows 2n, 2n+1 (every load of the thread in flight before the first DFT)
+    cx<T> v[NB][R];
 #pragma unroll
-        for (int r = 0; r < R / 2; ++r) {
-            const int n = j + r * NR;
-            v[r].re = (2 * n < Nt && live) ? xc[(int64_t)(2 * n) * in_row] : (T)0;
-            v[r].im = (2 * n + 1 < Nt && live) ? xc[(int64_t)(2 * n + 1) * in_row] : (T)0;
+    for (int b = 0; b < NB; ++b) {
+        const int jb = j + b * RSTEP;
+        if (jb < NR) {
+#pragma unroll
+            for (int r = 0; r < R / 2; ++r) {
+                const int n = jb + r * NR;
+                v[b][r].re = (2 * n < Nt && live) ? xc[(int64_t)(2 * n) * in_row] : (T)0;
+                v[b][r].im = (2 * n + 1 < Nt && live) ? xc[(int64_t)(2 * n + 1) * in_row] : (T)0;
+            }
         }
     }
     const cx<T>* tw = stage_twiddles<T>(tw_off, TWL, N, twg);
-    if (j < NR) {
-        Dft<R, -1, T>::run_hz(v);
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[((j * R + r) << LOGP) + c] = v[r];
+    for (int b = 0; b < NB; ++b) {
+        const int jb = j + b * RSTEP;
+        if (jb < NR) {
+            Dft<R, -1, T>::run_hz(v[b]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) sh[((jb * R + r) << LOGP) + c] = v[b][r];
+        }
     }
     __syncthreads();
     RestPasses<T, -1, FftCfg<T>::CMAX, TWL, PL>::run(LOGP, tw_off, twg);
@@ -825,27 +847,15 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
         const cx<T> E = cscale(cadd(Z, Zc), (T)0.5);
         const cx<T> O = cmul_i<-1>(cscale(csub(Z, Zc), (T)0.5));
         const cx<T> Tw = cmul(tw[f], O);
-        const cx<T> X0 = cadd(E, Tw), X1 = cconj(csub(E, Tw));
-        if constexpr ((8 << LOGP) >= 64) {  // runs of >= 64 bytes per row: non-temporal (see put_nt)
-            typedef float f2v __attribute__((ext_vector_type(2)));
-            __builtin_nontemporal_store(f2v{X0.re, X0.im}, (gptr<f2v>)q0);
-            if (2 * f != N) __builtin_nontemporal_store(f2v{X1.re, X1.im}, (gptr<f2v>)q1);
-        } else {
-            q0->re = X0.re;
-            q0->im = X0.im;
-            if (2 * f != N) {
-                q1->re = X1.re;
-                q1->im = X1.im;
-            }
-        }
+        put_vec<T, LOGP>(q0, cadd(E, Tw));
+        if (2 * f != N) put_vec<T, LOGP>(q1, cconj(csub(E, Tw)));
     }
 }
 
-template <typename PL, int LOGP>
+template <typename T, typename PL, int LOGP>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vc2r(
-    const cx<float>* __restrict__ in, int64_t in_row, int64_t in_batch, PtrBatch out, int64_t out_row, PtrBatch add,
-    float add_scale, int Nt, int ncols, const cx<float>* __restrict__ twg, float out_scale) {
-    typedef float T;
+    const cx<T>* __restrict__ in, int64_t in_row, int64_t in_batch, PtrBatch out, int64_t out_row, PtrBatch add,
+    T add_scale, int Nt, int ncols, const cx<T>* __restrict__ twg, T out_scale) {
     constexpr int N = PL::N, P = 1 << LOGP;
     constexpr int RSTEP = kFftThreads >> LOGP;
     constexpr bool TWL = ct_twl<T>(N);
@@ -918,7 +928,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
             const T v = out_scale * shr[2 * (((jr >> 1) << LOGP) + c) + (jr & 1)];
             const T w = ab ? fma(add_scale, av[u], v) : v;
             const gptr<T> q = xcol + (int64_t)jr * out_row;
-            if constexpr ((4 << LOGP) >= 64)
+            if constexpr ((sizeof(T) << LOGP) >= 64)
                 __builtin_nontemporal_store(w, q);
             else
                 *q = w;
@@ -926,16 +936,21 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 
     }
 }
 
-// Plans the fused kernels take at the widest tile: the forward one needs an even first radix
-// and one first-pass butterfly per thread; the inverse one takes every compile-time plan.
-template <typename PL>
+// Plans the fused kernels take at the widest tile, as measured against the general kernels.
+// Forward: an even first radix, in FP32 one first-pass butterfly per thread, in FP64 a tile of
+// at least four columns (FP64 N = 420 and 1000: 12-20 % faster; N = 2000, two columns, where
+// the first-pass loads sit in half the waves: 5 % slower).  Inverse: every FP32 plan; in FP64
+// tiles of at most four columns (N = 1000 and 2000: 5-7 % faster) and wider ones for several
+// vectors (N = 420, eight columns: 6-10 % faster for 8-64 vectors, 5 % slower for one).
+template <typename T, typename PL>
 constexpr bool vec_fused_r2c() {
-    constexpr int lp = ct_log_cols<float>(PL::N);
-    return FirstRadix<PL>::value % 2 == 0 && (PL::N / FirstRadix<PL>::value) << lp <= kFftThreads;
+    constexpr int lp = ct_log_cols<T>(PL::N);
+    return FirstRadix<PL>::value % 2 == 0 &&
+           (sizeof(T) == 8 ? lp >= 2 : (PL::N / FirstRadix<PL>::value) << lp <= kFftThreads);
 }
-template <typename PL>
-constexpr bool vec_fused_c2r() {
-    return true;
+template <typename T, typename PL>
+constexpr bool vec_fused_c2r(int nb) {
+    return sizeof(T) == 4 || ct_log_cols<T>(PL::N) <= 2 || nb > 1;
 }
 
 // Data side: reduce split partial sums over spans, inverse transform, keep j < Nt, scale;
@@ -1117,9 +1132,9 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
         // compile-time plans at their widest tile: the fused fixed-tile kernel
 #define BT_R2C_V(PLAN)                                                                                    \
     do {                                                                                                  \
-        if constexpr (vec_fused_r2c<PLAN>()) {                                                            \
+        if constexpr (vec_fused_r2c<float, PLAN>()) {                                                     \
             if (lp == ct_log_cols<float>(PLAN::N)) {                                                      \
-                k_vr2c<PLAN, ct_log_cols<float>(PLAN::N)><<<grid, block, lds, st>>>(                      \
+                k_vr2c<float, PLAN, ct_log_cols<float>(PLAN::N)><<<grid, block, lds, st>>>(               \
                     in, in_row, (cx<float>*)out, out_row, out_batch, Nt, ncols, (const cx<float>*)tw);    \
                 break;                                                                                    \
             }                                                                                             \
@@ -1139,13 +1154,25 @@ hipError_t launch_fft_r2c(Real r, Real ir, Stor os, const PtrBatch& in, int64_t 
 #define BT_R2C64(PLAN)                                                                                   \
     k_fft_r2c<double, double, cx<double>, PLAN><<<grid, block, lds, st>>>(                               \
         in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, plan, lp, (const cx<double>*)tw, twl, 0)
+#define BT_R2C64_V(PLAN)                                                                                  \
+    do {                                                                                                  \
+        if constexpr (vec_fused_r2c<double, PLAN>()) {                                                    \
+            if (lp == ct_log_cols<double>(PLAN::N)) {                                                     \
+                k_vr2c<double, PLAN, ct_log_cols<double>(PLAN::N)><<<grid, block, lds, st>>>(             \
+                    in, in_row, (cx<double>*)out, out_row, out_batch, Nt, ncols, (const cx<double>*)tw);  \
+                break;                                                                                    \
+            }                                                                                             \
+        }                                                                                                 \
+        BT_R2C64(PLAN);                                                                                   \
+    } while (0)
         switch (static_plan_id(plan, r)) {
 #define BT_CASE(ID, PLAN) \
-    case ID: BT_R2C64(PLAN); break;
+    case ID: BT_R2C64_V(PLAN); break;
             BT_STATIC_PLANS64(BT_CASE)
 #undef BT_CASE
             default: BT_R2C64(RuntimePlan); break;
         }
+#undef BT_R2C64_V
 #undef BT_R2C64
     } else {
         return hipErrorInvalidValue;
@@ -1213,13 +1240,11 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
                                                      twl, (float)out_scale, (4 << lp) >= 64)
 #define BT_C2R_V(PLAN)                                                                                     \
     do {                                                                                                   \
-        if constexpr (vec_fused_c2r<PLAN>()) {                                                             \
-            if (lp == ct_log_cols<float>(PLAN::N)) {                                                       \
-                k_vc2r<PLAN, ct_log_cols<float>(PLAN::N)><<<grid, block, lds, st>>>(                       \
-                    (const cx<float>*)in, in_row, in_batch, out, out_row, add, (float)add_scale, Nt, ncols, \
-                    (const cx<float>*)tw, (float)out_scale);                                               \
-                break;                                                                                     \
-            }                                                                                              \
+        if (lp == ct_log_cols<float>(PLAN::N) && vec_fused_c2r<float, PLAN>(nb)) {                         \
+            k_vc2r<float, PLAN, ct_log_cols<float>(PLAN::N)><<<grid, block, lds, st>>>(                    \
+                (const cx<float>*)in, in_row, in_batch, out, out_row, add, (float)add_scale, Nt, ncols,     \
+                (const cx<float>*)tw, (float)out_scale);                                                   \
+            break;                                                                                         \
         }                                                                                                  \
         BT_C2R(PLAN);                                                                                      \
     } while (0)
@@ -1237,13 +1262,24 @@ hipError_t launch_fft_c2r(Real r, const void* in, int64_t in_row, int64_t in_bat
     k_fft_c2r<double, PLAN><<<grid, block, lds, st>>>((const cx<double>*)in, in_row, in_batch, out, out_row, add, \
                                                       add_scale, Nt, ncols, plan, lp, (const cx<double>*)tw, twl, \
                                                       out_scale, (8 << lp) >= 64)
+#define BT_C2R64_V(PLAN)                                                                                    \
+    do {                                                                                                    \
+        if (lp == ct_log_cols<double>(PLAN::N) && vec_fused_c2r<double, PLAN>(nb)) {                         \
+            k_vc2r<double, PLAN, ct_log_cols<double>(PLAN::N)><<<grid, block, lds, st>>>(                   \
+                (const cx<double>*)in, in_row, in_batch, out, out_row, add, add_scale, Nt, ncols,           \
+                (const cx<double>*)tw, out_scale);                                                          \
+            break;                                                                                          \
+        }                                                                                                   \
+        BT_C2R64(PLAN);                                                                                     \
+    } while (0)
         switch (static_plan_id(plan, r)) {
 #define BT_CASE(ID, PLAN) \
-    case ID: BT_C2R64(PLAN); break;
+    case ID: BT_C2R64_V(PLAN); break;
             BT_STATIC_PLANS64(BT_CASE)
 #undef BT_CASE
             default: BT_C2R64(RuntimePlan); break;
         }
+#undef BT_C2R64_V
 #undef BT_C2R64
     }
     return hipGetLastError();
