@@ -153,6 +153,32 @@ def test_multi_rhs_matrix_cores(bt, shape, k, storage):
         assert oracle.rel_l2(HM[r], HM_ref[r]) <= tol, ("H", r)
 
 
+# FP64 series lengths with compile-time plans, one and several vectors: the launchers pick the
+# fused or the general transform kernels by tile width and vector count, so both meet here
+# (N = 420: 8-column tiles, N = 1000: 4, N = 2000: 2), with ragged column tiles.
+@pytest.mark.parametrize("shape", [(420, 3, 1111), (1000, 2, 129), (2000, 3, 77)])
+@pytest.mark.parametrize("k", [1, 3])
+def test_fp64_transforms_by_vector_count(bt, shape, k):
+    Nt, Nd, Nm = shape
+    print("case fp64 transforms", shape, k, flush=True)
+    rng = np.random.default_rng(Nt + Nd + Nm + 100 * k)
+    blocks = rng.standard_normal((Nt, Nd, Nm)) * np.exp(-np.arange(Nt) / (Nt / 7))[:, None, None]
+    op = make(bt, blocks, "f64")
+    M = rng.standard_normal((k, Nt, Nm))
+    D = rng.standard_normal((k, Nt, Nd))
+    Md, Dd = to_dev(M, torch.float64), to_dev(D, torch.float64)
+    FM = bt.btoep_apply_F(op, Md).cpu().numpy()
+    FTD = bt.btoep_apply_FT(op, Dd).cpu().numpy()
+    HM = bt.btoep_apply_H(op, Md, 2.0, 0.5).cpu().numpy()
+    FM_ref = oracle.apply_F(blocks, M)
+    FTD_ref = oracle.apply_FT(blocks, D)
+    HM_ref = oracle.apply_H(blocks, M, 2.0, 0.5)
+    for r in range(k):
+        assert oracle.rel_l2(FM[r], FM_ref[r]) <= TOL["f64"], ("F", r)
+        assert oracle.rel_l2(FTD[r], FTD_ref[r]) <= TOL["f64"], ("FT", r)
+        assert oracle.rel_l2(HM[r], HM_ref[r]) <= TOL["f64"], ("H", r)
+
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("storage", ["f32", "f32split", "bf16"])
 def test_multi_rhs_on_a_wide_launch(bt, storage):
